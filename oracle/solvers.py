@@ -1,0 +1,106 @@
+"""Textbook FP64 solvers for the even-odd system (oracle).
+
+The paper (Sec. 2) only says that iterative Krylov solvers are used and that
+their cost is dominated by multiplications by the fermion matrix; it names no
+algorithm.  The oracle uses the standard ones:
+
+* CGLS (conjugate gradients on the normal equations M^dag M x = M^dag b,
+  carrying the residual s = b - M x of the original system) to solve M x = b;
+* CG on the Hermitian positive definite operator A = M^dag M to solve A x = b;
+* defect correction (iterative refinement): x += solve(b - M x) with the inner
+  solve run to a loose relative tolerance;
+* dense ``numpy.linalg.solve`` on tiny lattices.
+
+Each solver takes the operators as callables on one-parity arrays.  Residuals
+are ||b - M x||_2 / ||b||_2 recomputed from scratch at the end.
+"""
+import numpy as np
+
+
+def vdot(a, b):
+    return np.vdot(a.reshape(-1), b.reshape(-1))
+
+
+def norm2(a):
+    return float(np.vdot(a.reshape(-1), a.reshape(-1)).real)
+
+
+def rel_resid(apply_op, x, b):
+    r = b - apply_op(x)
+    return np.sqrt(norm2(r) / norm2(b))
+
+
+def cgls(apply_m, apply_mdag, b, tol, maxiter, x0=None):
+    """Solve M x = b by CG on M^dag M x = M^dag b.
+
+    Stops when the recursive residual ||s|| <= tol * ||b|| (s = b - M x).
+    Returns (x, iterations, history of ||s||/||b||).
+    """
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    s = b - apply_m(x) if x0 is not None else b.copy()
+    r = apply_mdag(s)
+    p = r.copy()
+    gamma = norm2(r)
+    bnorm = np.sqrt(norm2(b))
+    hist = [np.sqrt(norm2(s)) / bnorm]
+    it = 0
+    while hist[-1] > tol and it < maxiter:
+        q = apply_m(p)
+        alpha = gamma / norm2(q)
+        x = x + alpha * p
+        s = s - alpha * q
+        r = apply_mdag(s)
+        gamma_new = norm2(r)
+        beta = gamma_new / gamma
+        gamma = gamma_new
+        p = r + beta * p
+        it += 1
+        hist.append(np.sqrt(norm2(s)) / bnorm)
+    return x, it, hist
+
+
+def cg(apply_a, b, tol, maxiter, x0=None):
+    """Solve A x = b for Hermitian positive definite A by plain CG."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - apply_a(x) if x0 is not None else b.copy()
+    p = r.copy()
+    rr = norm2(r)
+    bnorm = np.sqrt(norm2(b))
+    hist = [np.sqrt(rr) / bnorm]
+    it = 0
+    while hist[-1] > tol and it < maxiter:
+        q = apply_a(p)
+        alpha = rr / float(vdot(p, q).real)
+        x = x + alpha * p
+        r = r - alpha * q
+        rr_new = norm2(r)
+        beta = rr_new / rr
+        rr = rr_new
+        p = r + beta * p
+        it += 1
+        hist.append(np.sqrt(rr) / bnorm)
+    return x, it, hist
+
+
+def defect_correction(apply_m, inner_solve, b, tol, max_outer, x0=None):
+    """Iterative refinement: r = b - M x; x += inner_solve(r); repeat.
+
+    ``inner_solve(r)`` returns an approximate solution of M e = r.  Stops when
+    the true relative residual is <= tol.  Returns (x, outer iterations,
+    history of true relative residuals).
+    """
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    bnorm = np.sqrt(norm2(b))
+    r = b - apply_m(x)
+    hist = [np.sqrt(norm2(r)) / bnorm]
+    k = 0
+    while hist[-1] > tol and k < max_outer:
+        x = x + inner_solve(r)
+        r = b - apply_m(x)
+        k += 1
+        hist.append(np.sqrt(norm2(r)) / bnorm)
+    return x, k, hist
+
+
+def dense_solve(d, rhs):
+    return np.linalg.solve(d, rhs)

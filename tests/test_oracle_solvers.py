@@ -1,0 +1,71 @@
+"""Pins of the oracle's solvers: dense solutions, true residuals, and honest
+failure on an exactly singular operator."""
+import numpy as np
+
+from oracle import solvers as S
+from oracle import wilson as W
+from paper_2303_08609_amd import inputs
+
+PH = np.array([1, 1, 1, -1], dtype=np.complex128)
+
+
+def _dense_m(u, kappa, phases, dims):
+    vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    shape = (dims[3], dims[2], dims[1], dims[0] // 2, 4, 3)
+    n = 12 * vh
+    cols = [W.apply_m(u, np.eye(1, n, j, dtype=np.complex128).reshape(shape),
+                      kappa, phases).reshape(-1) for j in range(n)]
+    return np.array(cols).T
+
+
+def _setup(dims=(4, 4, 2, 4), kappa=0.125, eps=0.3, seeds=(101, 102)):
+    u = inputs.gen_gauge(dims, eps, seeds[0])
+    b = inputs.gen_spinor_half(dims, seeds[1])
+    m = lambda v: W.apply_m(u, v, kappa, PH)
+    md = lambda v: W.apply_m(u, v, kappa, PH, dagger=True)
+    return u, b, m, md, dims, kappa
+
+
+def test_cgls_matches_dense_solution():
+    u, b, m, md, dims, kappa = _setup()
+    x, it, hist = S.cgls(m, md, b, 1e-12, 2000)
+    assert hist[-1] <= 1e-12 and it > 5
+    assert S.rel_resid(m, x, b) < 5e-12
+    d = _dense_m(u, kappa, PH, dims)
+    xd = S.dense_solve(d, b.reshape(-1)).reshape(b.shape)
+    cond = np.linalg.cond(d)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 10 * cond * 1e-12
+
+
+def test_cg_normal_matches_dense_solution():
+    u, b, m, md, dims, kappa = _setup()
+    a = lambda v: md(m(v))
+    x, it, hist = S.cg(a, b, 1e-12, 2000)
+    assert S.rel_resid(a, x, b) < 1e-11
+    d = _dense_m(u, kappa, PH, dims)
+    xd = np.linalg.solve(np.conj(d.T) @ d, b.reshape(-1)).reshape(b.shape)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-9
+
+
+def test_defect_correction_reaches_tight_tolerance_with_loose_inner():
+    u, b, m, md, dims, kappa = _setup(eps=0.5)
+    inner = lambda r: S.cgls(m, md, r, 1e-3, 1000)[0]
+    x, k, hist = S.defect_correction(m, inner, b, 1e-12, 20)
+    assert hist[-1] <= 1e-12 and k >= 3
+    # each outer step gains about the inner tolerance
+    for a, c in zip(hist[1:-1], hist[2:]):
+        assert c < 1e-2 * a
+    # a given start resumes to the same tolerance
+    x2, k2, hist2 = S.defect_correction(m, inner, b, 1e-12, 20, x0=x)
+    assert k2 == 0 and hist2[0] <= 1e-12
+
+
+def test_cgls_reports_non_convergence_on_singular_operator():
+    dims = (4, 4, 2, 4)
+    u = inputs.gen_unit_gauge(dims)
+    b = inputs.gen_spinor_half(dims, 7)
+    m = lambda v: W.apply_m(u, v, 0.125, np.ones(4))
+    md = lambda v: W.apply_m(u, v, 0.125, np.ones(4), dagger=True)
+    x, it, hist = S.cgls(m, md, b, 1e-10, 300)
+    assert it == 300 and hist[-1] > 1e-3
+    assert S.rel_resid(m, x, b) > 1e-3

@@ -1,0 +1,312 @@
+"""Pins of the oracle's Wilson operator (paper Sec. 2, Eqs. (1)-(5)).
+
+Each test ties the oracle to something it does not compute itself: the
+free-field closed forms, the adjoint relation, gauge and translation
+covariance, a dense assembly from the component formula of the footnote to
+Eq. (1), and algebraic special cases.  A sign, index, phase or transposition
+mistake in ``oracle.wilson`` breaks at least one of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+from scipy.optimize import linear_sum_assignment
+
+from oracle import wilson as W
+from oracle.gamma import GAMMA, GAMMA5
+from oracle.lattice import full_to_half, half_to_full, parity_mask
+from paper_2303_08609_amd import inputs
+
+PHASES_AP = np.array([1, 1, 1, -1], dtype=np.complex128)
+
+
+def _rand_phases(seed):
+    th = np.random.default_rng(seed).uniform(0, 2 * np.pi, 4)
+    return np.exp(1j * th)
+
+
+def _vdot(a, b):
+    return np.vdot(a.reshape(-1), b.reshape(-1))
+
+
+def _match_multisets(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    assert a.shape == b.shape
+    cost = np.abs(a[:, None] - b[None, :])
+    r, c = linear_sum_assignment(cost)
+    return cost[r, c].max()
+
+
+def _momenta(dims, thetas):
+    grids = [(2 * np.pi * np.arange(L) + th) / L for L, th in zip(dims, thetas)]
+    return np.array(list(itertools.product(*grids)))
+
+
+def _free_dw_eigs(dims, kappa, thetas):
+    ev = []
+    for p in _momenta(dims, thetas):
+        c = np.cos(p).sum()
+        s = np.sqrt((np.sin(p) ** 2).sum())
+        ev += [1 - 2 * kappa * c + 2j * kappa * s] * 6
+        ev += [1 - 2 * kappa * c - 2j * kappa * s] * 6
+    return np.array(ev)
+
+
+def _free_m_eigs(dims, kappa, thetas):
+    ev = []
+    for p in _momenta(dims, thetas):
+        c = np.cos(p).sum()
+        s = np.sqrt((np.sin(p) ** 2).sum())
+        for sg in (1, -1):
+            ev += [1 - kappa ** 2 * (2 * c - 2j * sg * s) ** 2] * 6
+    ev = np.array(ev)
+    # every value appears twice (p and p + (pi,pi,pi,pi)): keep half; round
+    # first so that equal values sort next to each other
+    order = np.lexsort((np.round(ev.imag, 9), np.round(ev.real, 9)))
+    return ev[order][::2]
+
+
+def _dense_m(u, kappa, phases, dims):
+    vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    shape = (dims[3], dims[2], dims[1], dims[0] // 2, 4, 3)
+    n = 12 * vh
+    m = np.zeros((n, n), dtype=np.complex128)
+    for j in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[j] = 1
+        m[:, j] = W.apply_m(u, e.reshape(shape), kappa, phases).reshape(-1)
+    return m
+
+
+# --- dense second route -----------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 2, 2, 4), (2, 4, 4, 2)])
+def test_hop_matches_dense_component_formula(dims):
+    u = inputs.gen_gauge(dims, 0.7, 11)
+    ph = _rand_phases(3)
+    psi = inputs.gen_spinor_full(dims, 12)
+    h = W.dense_hop(u, ph)
+    for dag in (False, True):
+        got = W.hop(u, psi, ph, dagger=dag).reshape(-1)
+        want = (np.conj(h.T) if dag else h) @ psi.reshape(-1)
+        assert np.abs(got - want).max() < 1e-13
+
+
+def test_eo_blocks_match_dense():
+    dims = (4, 2, 2, 4)
+    u = inputs.gen_gauge(dims, 0.5, 13)
+    h = W.dense_hop(u, PHASES_AP)
+    re, ro = W.dense_parity_rows(dims, 0), W.dense_parity_rows(dims, 1)
+    psi_e = inputs.gen_spinor_half(dims, 14)
+    got = W.hop_eo(u, psi_e, 0, PHASES_AP).reshape(-1)
+    assert np.abs(got - h[np.ix_(ro, re)] @ psi_e.reshape(-1)).max() < 1e-13
+    psi_o = inputs.gen_spinor_half(dims, 15)
+    got = W.hop_eo(u, psi_o, 1, PHASES_AP).reshape(-1)
+    assert np.abs(got - h[np.ix_(re, ro)] @ psi_o.reshape(-1)).max() < 1e-13
+    # same-parity blocks of H vanish: the hop only couples opposite parities
+    assert np.abs(h[np.ix_(re, re)]).max() == 0
+    assert np.abs(h[np.ix_(ro, ro)]).max() == 0
+
+
+# --- P1 free-field spectrum -------------------------------------------------
+
+@pytest.mark.parametrize("dims,thetas", [
+    ((2, 2, 2, 2), (0, 0, 0, np.pi)),
+    ((2, 4, 2, 4), (0.3, 0, 1.1, np.pi)),
+])
+def test_free_field_dw_spectrum(dims, thetas):
+    kappa = 0.13
+    u = inputs.gen_unit_gauge(dims)
+    d = W.dense_dirac_wilson(u, kappa, np.exp(1j * np.array(thetas)))
+    got = np.linalg.eigvals(d)
+    assert _match_multisets(got, _free_dw_eigs(dims, kappa, thetas)) < 1e-10
+
+
+@pytest.mark.parametrize("dims,thetas", [
+    ((2, 2, 2, 2), (0, 0, 0, np.pi)),
+    ((2, 4, 2, 4), (0, 0, 0, np.pi)),
+    ((4, 4, 4, 4), (0, 0, 0, np.pi)),
+])
+def test_free_field_m_spectrum(dims, thetas):
+    kappa = 0.125
+    u = inputs.gen_unit_gauge(dims)
+    m = _dense_m(u, kappa, np.exp(1j * np.array(thetas)), dims)
+    got = np.linalg.eigvals(m)
+    assert _match_multisets(got, _free_m_eigs(dims, kappa, thetas)) < 1e-10
+
+
+# --- P2 plane wave, fixes the projector sign convention ----------------------
+
+@pytest.mark.parametrize("dims", [(4, 6, 2, 8), (8, 4, 4, 4)])
+def test_plane_wave_eigen_action(dims):
+    kappa = 0.126
+    thetas = np.array([0, 0, 0, np.pi])
+    ph = np.exp(1j * thetas)
+    u = inputs.gen_unit_gauge(dims)
+    rng = np.random.default_rng(1)
+    n = [rng.integers(L) for L in dims]
+    p = (2 * np.pi * np.array(n) + thetas) / np.array(dims)
+    k = sum(GAMMA[mu] * np.sin(p[mu]) for mu in range(4))
+    w, v = np.linalg.eigh(k)
+    s = np.sqrt((np.sin(p) ** 2).sum())
+    c = np.cos(p).sum()
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(range(lt), range(lz), range(ly), range(lx), indexing="ij")
+    phase = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+    col = np.array([0.3, -0.2j, 0.9])
+    for idx in (0, 3):
+        sigma = np.sign(w[idx]) if s > 1e-12 else 1.0
+        spinor = np.outer(v[:, idx], col)
+        full = phase[..., None, None] * spinor
+        psi_e = full_to_half(full, 0)
+        lam = 1 - kappa ** 2 * (2 * c - 2j * sigma * s) ** 2
+        got = W.apply_m(u, psi_e, kappa, ph)
+        assert np.abs(got - lam * psi_e).max() < 1e-12
+
+
+# --- P3 adjoint and gamma5-hermiticity ---------------------------------------
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 6, 2, 8), (6, 4, 8, 2)])
+def test_adjoint_and_gamma5_hermiticity(dims):
+    kappa = 0.124
+    u = inputs.gen_gauge(dims, 0.5, 21)
+    ph = _rand_phases(4)
+    psi = inputs.gen_spinor_half(dims, 22)
+    chi = inputs.gen_spinor_half(dims, 23)
+    mpsi = W.apply_m(u, psi, kappa, ph)
+    mdchi = W.apply_m(u, chi, kappa, ph, dagger=True)
+    assert abs(_vdot(chi, mpsi) - _vdot(mdchi, psi)) < 1e-12 * abs(_vdot(chi, mpsi))
+    g5mg5 = W.gamma5_half(W.apply_m(u, W.gamma5_half(chi), kappa, ph))
+    assert np.abs(g5mg5 - mdchi).max() < 1e-13
+    # hop blocks: (P_o H P_e)^dag = P_e H^dag P_o
+    o = inputs.gen_spinor_half(dims, 24)
+    lhs = _vdot(o, W.hop_eo(u, psi, 0, ph))
+    rhs = _vdot(W.hop_eo(u, o, 1, ph, dagger=True), psi)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+# --- P4 gauge covariance ------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 6, 2, 8)])
+def test_gauge_covariance(dims):
+    kappa = 0.125
+    u = inputs.gen_gauge(dims, 0.5, 31)
+    om = inputs.gen_su3_random(dims, 32)
+    up = np.empty_like(u)
+    for mu in range(4):
+        om_fwd = np.roll(om, -1, axis=3 - mu)   # Omega(x + mu)
+        up[mu] = om @ u[mu] @ np.conj(np.swapaxes(om_fwd, -1, -2))
+    psi = inputs.gen_spinor_half(dims, 33)
+    om_e = full_to_half(om, 0)
+    rot = lambda o, s: np.einsum("...ab,...sb->...sa", o, s)
+    got = W.apply_m(up, rot(om_e, psi), kappa, PHASES_AP)
+    want = rot(om_e, W.apply_m(u, psi, kappa, PHASES_AP))
+    assert np.abs(got - want).max() < 1e-13
+
+
+# --- P5 Schur complement vs the dense full system -----------------------------
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4)])
+def test_schur_determinant_and_solution(dims):
+    kappa = 0.125
+    u = inputs.gen_gauge(dims, 0.3, 101)
+    d = W.dense_dirac_wilson(u, kappa, PHASES_AP)
+    m = _dense_m(u, kappa, PHASES_AP, dims)
+    s1, l1 = np.linalg.slogdet(d)
+    s2, l2 = np.linalg.slogdet(m)
+    assert abs(l1 - l2) < 1e-10 and abs(s1 - s2) < 1e-10
+    # full solve D xi = eta versus Eq. (4) then Eq. (5)
+    eta = inputs.gen_spinor_full(dims, 102)
+    xi = np.linalg.solve(d, eta.reshape(-1)).reshape(eta.shape)
+    eta_e, eta_o = full_to_half(eta, 0), full_to_half(eta, 1)
+    b_e = eta_e + kappa * W.hop_eo(u, eta_o, 1, PHASES_AP)
+    xi_e = np.linalg.solve(m, b_e.reshape(-1)).reshape(b_e.shape)
+    xi_o = eta_o + kappa * W.hop_eo(u, xi_e, 0, PHASES_AP)
+    assert np.abs(xi_e - full_to_half(xi, 0)).max() < 1e-12
+    assert np.abs(xi_o - full_to_half(xi, 1)).max() < 1e-12
+
+
+# --- P6 single-direction isometry ---------------------------------------------
+
+def test_single_direction_isometry():
+    dims = (4, 6, 2, 8)
+    u = inputs.gen_gauge(dims, 0.9, 41)
+    ph = _rand_phases(5)
+    psi = inputs.gen_spinor_full(dims, 42)
+    nrm = np.linalg.norm(psi)
+    for mu in range(4):
+        for dag in (False, True):
+            out = W.hop(u, psi, ph, dagger=dag, dirs=(mu,))
+            assert abs(np.linalg.norm(out) - 2 * nrm) < 1e-12 * nrm
+    full = W.hop(u, psi, ph)
+    assert np.linalg.norm(full) <= 8 * nrm
+
+
+# --- P7 special cases ----------------------------------------------------------
+
+def test_special_cases():
+    dims = (4, 4, 2, 4)
+    u = inputs.gen_gauge(dims, 0.5, 51)
+    psi = inputs.gen_spinor_half(dims, 52)
+    chi = inputs.gen_spinor_half(dims, 53)
+    assert np.array_equal(W.apply_m(u, psi, 0.0, PHASES_AP), psi)
+    a, b = 0.3 - 1.2j, 2.1 + 0.4j
+    lin = W.apply_m(u, a * psi + b * chi, 0.12, PHASES_AP)
+    want = a * W.apply_m(u, psi, 0.12, PHASES_AP) + b * W.apply_m(u, chi, 0.12, PHASES_AP)
+    assert np.abs(lin - want).max() < 1e-13
+    # periodic vs antiperiodic t differ only where a hop crosses the t edge
+    full = inputs.gen_spinor_full(dims, 54)
+    hp = W.hop(u, full, np.ones(4))
+    ha = W.hop(u, full, PHASES_AP)
+    diff = np.abs(hp - ha).max(axis=(1, 2, 3, 4, 5))
+    assert np.all(diff[1:-1] == 0) and diff[0] > 0 and diff[-1] > 0
+
+
+def test_zero_mode_at_critical_kappa():
+    dims = (4, 4, 4, 4)
+    u = inputs.gen_unit_gauge(dims)
+    const = np.ones((4, 4, 4, 2, 4, 3), dtype=np.complex128)
+    out = W.apply_m(u, const, 0.125, np.ones(4))
+    assert np.abs(out).max() < 1e-14
+
+
+# --- P8 translation covariance -------------------------------------------------
+
+def test_translation_covariance():
+    dims = (4, 6, 4, 4)
+    u = inputs.gen_gauge(dims, 0.5, 61)
+    full = half_to_full(inputs.gen_spinor_half(dims, 62), 0, dims)
+    shift = (1, 1, 2)          # x, y, z: even total keeps the parity
+    axes = (3, 2, 1)
+    tr = lambda a, off=0: np.roll(a, shift, axis=tuple(ax + off for ax in axes))
+    ut = np.stack([tr(u[mu]) for mu in range(4)])
+    out = W.apply_m(u, full_to_half(full, 0), 0.12, PHASES_AP)
+    out_t = W.apply_m(ut, full_to_half(tr(full), 0), 0.12, PHASES_AP)
+    assert np.array_equal(full_to_half(tr(half_to_full(out, 0, dims)), 0), out_t)
+
+
+# --- per-site evaluation used for sampled checks ------------------------------
+
+def test_site_evaluation_matches_full():
+    dims = (4, 6, 2, 8)
+    u = inputs.gen_gauge(dims, 0.5, 71)
+    ph = _rand_phases(6)
+    psi = inputs.gen_spinor_half(dims, 72)
+    vh = 4 * 6 * 2 * 8 // 2
+    idx = [0, 1, 5, vh // 2, vh - 1]
+    for dag in (False, True):
+        full = W.apply_m(u, psi, 0.126, ph, dagger=dag).reshape(vh, 4, 3)
+        got = W.apply_m_at_sites(u, psi, 0.126, ph, idx, dagger=dag)
+        assert np.abs(got - full[idx]).max() < 1e-13
+        for p in (0, 1):
+            hfull = W.hop_eo(u, psi, p, ph, dagger=dag).reshape(vh, 4, 3)
+            hsite = W.hop_at_sites(u, psi, p, ph, idx, dagger=dag)
+            assert np.abs(hsite - hfull[idx]).max() < 1e-13
+
+
+def test_parity_mask_counts():
+    dims = (4, 6, 2, 8)
+    e = parity_mask(dims, 0)
+    assert e.sum() == e.size // 2 and (~e).sum() == e.size // 2
+    assert e[0, 0, 0, 0]
