@@ -1,0 +1,211 @@
+/*
+ * wilson_eo.h -- C ABI of libwilson_eo.so, the even-odd preconditioned Wilson
+ * fermion operator on AMD MI355X (gfx950).
+ *
+ * The operator (Kanamori, Nitadori, Matsufuru, HPCAsia 2023 Workshops,
+ * arXiv:2303.08609, Sec. 2):
+ *
+ *   Eq. (1):  D_W = 1 - kappa H,
+ *             H(x,y) = sum_mu [ (1 - gamma_mu) U_mu(x) delta_{x+mu,y}
+ *                             + (1 + gamma_mu) U_mu(x-mu)^dag delta_{x-mu,y} ]
+ *   Eqs. (3)-(4) with D_ee = D_oo = 1 (Wilson):
+ *             M = 1 - kappa^2 H_eo H_oe   on the even sublattice,
+ *   where H_oe = P_o H P_e maps even sites to odd sites and H_eo = P_e H P_o.
+ *
+ * Conventions
+ *   - Lattice extents Lx, Ly, Lz, Lt; each even and >= 2.  x runs fastest.
+ *     A site is even when x+y+z+t is even.  The sites of one parity are
+ *     compacted along x (Sec. 3.3, Fig. 4): half index
+ *       ih = (x >> 1) + Lx/2 * (y + Ly * (z + Lz * t)).
+ *   - gamma matrices: Euclidean Dirac representation,
+ *       gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] (k = x, y, z),
+ *       gamma_t = diag(1, 1, -1, -1).
+ *   - Boundary conditions: a U(1) phase per direction.  A hop that crosses
+ *     the lattice edge forward is multiplied by bc[mu], backward by conj(bc[mu]).
+ *     Phases are applied inside the kernels, never folded into the links.
+ *   - "dagger" selects the Hermitian conjugate operator (H^dag swaps the two
+ *     projectors; M^dag = gamma5 M gamma5).
+ *   - Canonical host-side layouts (complex, interleaved re/im), accepted by the
+ *     pack/unpack calls in complex128 (WEO_F64) or complex64 (WEO_F32):
+ *       gauge   [4][Lt][Lz][Ly][Lx][3][3]        U_mu(x)_{ab}, mu = x,y,z,t
+ *       spinor  [nrhs][Lt][Lz][Ly][Lx/2][4][3]   one parity, [spin][colour]
+ *   - Packed device layouts are private to the library; size them with
+ *     weo_gauge_bytes / weo_spinor_bytes and fill them with the pack calls.
+ *
+ * Memory and streams
+ *   - Every buffer pointer is a DEVICE pointer owned by the caller; the library
+ *     never allocates, frees or retains caller memory.  Base pointers must be
+ *     256-byte aligned (WEO_ERR_ALIGN otherwise).  Input and output buffers
+ *     must not overlap (WEO_ERR_ARG where detectable).
+ *   - "stream" is a hipStream_t (NULL = the default stream).  pack, unpack,
+ *     hop, apply and force are asynchronous on that stream.  wilson_eo_cg
+ *     synchronises the stream before it returns.
+ *   - Errors are returned, never raised or aborted on; arguments are validated
+ *     before any HIP call is made.
+ */
+#ifndef WILSON_EO_H
+#define WILSON_EO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define WEO_OK              0
+#define WEO_ERR_ARG        -1   /* null pointer, bad enum, bad count, aliasing */
+#define WEO_ERR_DIMS       -2   /* an extent odd, < 2, or the volume too large */
+#define WEO_ERR_ALIGN      -3   /* a base pointer not 256-byte aligned */
+#define WEO_ERR_FORMAT     -4   /* precision / link-format combination not built */
+#define WEO_ERR_HIP        -5   /* a HIP runtime call failed */
+#define WEO_ERR_WORKSPACE  -6   /* workspace missing or smaller than required */
+#define WEO_NOT_CONVERGED   1   /* solver hit maxiter / max_outer; x is the best iterate */
+#define WEO_BREAKDOWN       2   /* solver met a non-positive or non-finite scalar */
+
+/* ---- precisions and link formats --------------------------------------- */
+#define WEO_F64   0
+#define WEO_F32   1
+#define WEO_F16   2
+#define WEO_BF16  3
+
+#define WEO_LINK18 0   /* all 9 complex entries stored */
+#define WEO_LINK12 1   /* rows 0 and 1 stored; row 2 = conj(row0 x row1),
+                          exact for det U = 1 (SU(3)) */
+
+#define WEO_MAX_RHS 16
+
+typedef struct {
+    int    dims[4];    /* Lx, Ly, Lz, Lt: each even and >= 2 */
+    double kappa;      /* hopping parameter, kappa = 1/(8 + 2m) (Sec. 2) */
+    double bc[4][2];   /* boundary phase (re, im) per direction x, y, z, t */
+} weo_lattice;
+
+/* Storage format of the fields an operation reads and writes.  Arithmetic is
+ * FP64 for WEO_F64 spinors and FP32 otherwise.  Built combinations
+ * (spinor_prec / link_prec / link_fmt):
+ *   F64/F64/18|12, F32/F32/18|12, F16/F16/18|12, BF16/F16/18|12.            */
+typedef struct {
+    int spinor_prec;
+    int link_prec;
+    int link_fmt;
+} weo_format;
+
+/* Human-readable text of a status code (static storage). */
+const char* wilson_eo_strerror(int code);
+
+/* Host-only self-test of the library's index arithmetic (fast division,
+ * even-odd site decoding, neighbour indices and boundary flags, workgroup
+ * remap) against direct coordinate arithmetic.  Needs no GPU.  Returns 0 on
+ * success, a positive code naming the failed check otherwise. */
+int weo_selftest(void);
+
+/* 1 if the format combination is built into this library, else 0. */
+int weo_format_supported(const weo_format* fmt);
+
+/* Bytes of the packed gauge field (all 4V links) in format fmt; 0 on error. */
+size_t weo_gauge_bytes(const weo_lattice* lat, const weo_format* fmt);
+
+/* Bytes of nrhs packed one-parity spinors (V/2 sites each); 0 on error. */
+size_t weo_spinor_bytes(const weo_lattice* lat, const weo_format* fmt, int nrhs);
+
+/* Convert a canonical gauge field (device memory, complex128 if canon_prec is
+ * WEO_F64, complex64 if WEO_F32) into the packed format fmt (links rounded to
+ * nearest even; WEO_LINK12 drops row 2).  Phases are not applied here. */
+int weo_pack_gauge(const weo_lattice* lat, const weo_format* fmt,
+                   const void* u_canon, int canon_prec,
+                   void* u_packed, void* stream);
+
+/* Convert nrhs canonical one-parity spinors into the packed format, multiplying
+ * by scale on the way (scale lets FP16 spinors be kept near unit magnitude). */
+int weo_pack_spinor(const weo_lattice* lat, const weo_format* fmt, int nrhs,
+                    const void* s_canon, int canon_prec, double scale,
+                    void* s_packed, void* stream);
+
+/* Inverse of weo_pack_spinor: canonical = packed * scale. */
+int weo_unpack_spinor(const weo_lattice* lat, const weo_format* fmt, int nrhs,
+                      const void* s_packed, double scale,
+                      void* s_canon, int canon_prec, void* stream);
+
+/* One hopping block (Eq. (1) off-diagonal part, paper Fig. 2, without -kappa):
+ *   out = P_{out_parity} H P_{1-out_parity} in      (dagger = 0)
+ *   out = P_{out_parity} H^dag P_{1-out_parity} in  (dagger = 1)
+ * in and out are nrhs packed spinors of parity 1-out_parity and out_parity. */
+int wilson_eo_hop(const weo_lattice* lat, const weo_format* fmt,
+                  int out_parity, int dagger,
+                  const void* u, const void* in, void* out,
+                  int nrhs, void* stream);
+
+/* The even-odd operator of Eq. (4), left-hand side, on the even sublattice:
+ *   out = M in = in - kappa^2 H_eo H_oe in   (dagger = 0)
+ *   out = M^dag in                           (dagger = 1)
+ * tmp is caller scratch for nrhs odd-parity spinors (weo_spinor_bytes). */
+int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger,
+                    const void* u, const void* in, void* out, void* tmp,
+                    int nrhs, void* stream);
+
+/* ---- solvers (the paper names none; Sec. 2 says solves dominate) -------- */
+#define WEO_OP_M      0   /* solve M x = b by CGLS (CG on the normal equations) */
+#define WEO_OP_MDAGM  1   /* solve M^dag M x = b by CG */
+
+typedef struct {
+    int        op;          /* WEO_OP_M or WEO_OP_MDAGM */
+    int        nrhs;        /* 1..WEO_MAX_RHS right-hand sides solved together */
+    double     tol;         /* target true relative residual ||b - A x|| / ||b|| */
+    int        maxiter;     /* cap on inner iterations (per solve) */
+    int        x0_given;    /* 1: x holds the initial guess; 0: start from zero */
+    int        mixed;       /* 0: iterate in format fmt.
+                               1: FP64 defect correction (fmt must be F64) with
+                                  inner solves in format `inner` on links u_inner */
+    weo_format inner;       /* inner format when mixed = 1 */
+    double     inner_tol;   /* relative tolerance of each inner solve */
+    int        max_outer;   /* cap on defect-correction steps */
+    int        check_every; /* iterations between host convergence checks (>=1) */
+} weo_solver_params;
+
+typedef struct {
+    int    status;                          /* WEO_OK, WEO_NOT_CONVERGED, WEO_BREAKDOWN */
+    int    iters;                           /* inner iterations performed */
+    int    outer_iters;                     /* defect-correction steps (mixed) */
+    int    applies;                         /* M or M^dag applications issued */
+    double true_rel_resid[WEO_MAX_RHS];     /* recomputed at exit, FP64 for mixed */
+    double seconds;                         /* wall time inside the call */
+} weo_solver_info;
+
+/* Bytes of device workspace wilson_eo_cg needs for these parameters. */
+size_t wilson_eo_cg_workspace_bytes(const weo_lattice* lat, const weo_format* fmt,
+                                    const weo_solver_params* p);
+
+/* Solve for nrhs right-hand sides b (packed, format fmt, even parity) into x.
+ * u holds the links in format fmt; u_inner the links in p->inner (mixed only,
+ * else ignored).  Synchronises `stream` before returning. */
+int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt,
+                 const weo_solver_params* p,
+                 const void* u, const void* u_inner,
+                 const void* b, void* x,
+                 void* workspace, size_t ws_bytes,
+                 weo_solver_info* info, void* stream);
+
+/* ---- derivatives --------------------------------------------------------- */
+/* Link gradient of coeff * Re <Lambda, H R> for full-lattice fields given as
+ * even and odd packed parts (1 rhs each).  For the link U_mu(x) with boundary
+ * phase b (bc[mu] where x_mu = L_mu - 1, else 1):
+ *   g = coeff * conj(b) * [ sum_s ((1-gamma_mu) Lambda(x))_s R(x+mu)_s^dag
+ *                         + sum_s R(x)_s ((1+gamma_mu) Lambda(x+mu))_s^dag ]
+ * which is d/dU in the convention dL = Re tr(g^dag dU).  With project = 1 the
+ * su(3) force F = TH(i U g^dag) is written instead (TH = traceless Hermitian
+ * part), so that dL/d eps = tr(X F) for U -> exp(i eps X) U.
+ * For L = Re<eta, M psi>: Lambda = (eta, H_eo^dag eta), R = (psi, H_oe psi),
+ * coeff = -kappa^2.  Output: canonical gauge layout in canon_prec. */
+int wilson_eo_force(const weo_lattice* lat, const weo_format* fmt,
+                    const void* u,
+                    const void* lam_e, const void* lam_o,
+                    const void* r_e, const void* r_o,
+                    double coeff, int project,
+                    void* g_canon, int canon_prec, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WILSON_EO_H */

@@ -1,0 +1,249 @@
+// extern "C" entry points of libwilson_eo: argument validation, format
+// tables and dispatch to the HIP launchers.  Host-only C++ (no kernels here):
+// every check runs before the first HIP call, so a bad argument never reaches
+// the device.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/wilson_eo.h"
+#include "weo_internal.h"
+
+namespace weo {
+
+static const FmtInfo k_fmt[FMT_COUNT] = {
+    // spinor, link, link12, spinor site bytes, link bytes, wide
+    {WEO_F64, WEO_F64, 0, 12 * 16, 9 * 16, 1},
+    {WEO_F64, WEO_F64, 1, 12 * 16, 6 * 16, 1},
+    {WEO_F32, WEO_F32, 0, 12 * 8, 9 * 8, 0},
+    {WEO_F32, WEO_F32, 1, 12 * 8, 6 * 8, 0},
+    {WEO_F16, WEO_F16, 0, 12 * 4, 9 * 4, 0},
+    {WEO_F16, WEO_F16, 1, 12 * 4, 6 * 4, 0},
+    {WEO_BF16, WEO_F16, 0, 12 * 4, 9 * 4, 0},
+    {WEO_BF16, WEO_F16, 1, 12 * 4, 6 * 4, 0},
+};
+
+const FmtInfo& fmt_info(int id) { return k_fmt[id]; }
+
+int format_id(const weo_format* f) {
+    if (!f) return -1;
+    if (f->link_fmt != WEO_LINK18 && f->link_fmt != WEO_LINK12) return -1;
+    for (int i = 0; i < FMT_COUNT; ++i)
+        if (k_fmt[i].spinor_prec == f->spinor_prec && k_fmt[i].link_prec == f->link_prec &&
+            k_fmt[i].link12 == (f->link_fmt == WEO_LINK12))
+            return i;
+    return -1;
+}
+
+// Largest supported sites per parity: keeps every plane below 2^31 bytes
+// so that per-lane 32-bit byte offsets cannot wrap.
+static const uint64_t k_max_vh = 1ull << 26;
+
+int check_lattice(const weo_lattice* lat, Geom* g) {
+    if (!lat) return WEO_ERR_ARG;
+    uint64_t v = 1;
+    for (int m = 0; m < 4; ++m) {
+        const int L = lat->dims[m];
+        if (L < 2 || (L & 1)) return WEO_ERR_DIMS;
+        v *= (uint64_t)L;
+        if (v > 2 * k_max_vh) return WEO_ERR_DIMS;
+        if (!std::isfinite(lat->bc[m][0]) || !std::isfinite(lat->bc[m][1])) return WEO_ERR_ARG;
+    }
+    if (!std::isfinite(lat->kappa)) return WEO_ERR_ARG;
+    if (g) *g = make_geom(lat->dims);
+    return WEO_OK;
+}
+
+int check_fmt(const weo_format* f, int* id) {
+    if (!f) return WEO_ERR_ARG;
+    const int known = (unsigned)f->spinor_prec <= WEO_BF16 && (unsigned)f->link_prec <= WEO_BF16 &&
+                      (f->link_fmt == WEO_LINK18 || f->link_fmt == WEO_LINK12);
+    if (!known) return WEO_ERR_ARG;
+    const int i = format_id(f);
+    if (i < 0) return WEO_ERR_FORMAT;
+    if (id) *id = i;
+    return WEO_OK;
+}
+
+int check_ptr(const void* p) {
+    if (!p) return WEO_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(p) & 255u) return WEO_ERR_ALIGN;
+    return WEO_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+void phases_of(const weo_lattice* lat, double ph[4][2]) {
+    for (int m = 0; m < 4; ++m) { ph[m][0] = lat->bc[m][0]; ph[m][1] = lat->bc[m][1]; }
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? WEO_OK : WEO_ERR_HIP; }
+
+}  // namespace weo
+
+using namespace weo;
+
+#define WEO_TRY(expr)                 \
+    do {                              \
+        const int _rc = (expr);       \
+        if (_rc != WEO_OK) return _rc; \
+    } while (0)
+
+extern "C" {
+
+const char* wilson_eo_strerror(int code) {
+    switch (code) {
+        case WEO_OK: return "ok";
+        case WEO_ERR_ARG: return "invalid argument (null pointer, bad enum or count, or overlapping buffers)";
+        case WEO_ERR_DIMS: return "invalid lattice extents (each must be even and >= 2; volume limited)";
+        case WEO_ERR_ALIGN: return "buffer base pointer not 256-byte aligned";
+        case WEO_ERR_FORMAT: return "precision / link-format combination not built into this library";
+        case WEO_ERR_HIP: return "HIP runtime error";
+        case WEO_ERR_WORKSPACE: return "workspace missing or too small";
+        case WEO_NOT_CONVERGED: return "solver did not reach the tolerance within its iteration caps";
+        case WEO_BREAKDOWN: return "solver breakdown (non-positive or non-finite scalar)";
+        default: return "unknown status code";
+    }
+}
+
+int weo_format_supported(const weo_format* fmt) { return format_id(fmt) >= 0 ? 1 : 0; }
+
+size_t weo_gauge_bytes(const weo_lattice* lat, const weo_format* fmt) {
+    Geom g;
+    int id;
+    if (check_lattice(lat, &g) != WEO_OK || check_fmt(fmt, &id) != WEO_OK) return 0;
+    return gauge_field_bytes(g, id);
+}
+
+size_t weo_spinor_bytes(const weo_lattice* lat, const weo_format* fmt, int nrhs) {
+    Geom g;
+    int id;
+    if (check_lattice(lat, &g) != WEO_OK || check_fmt(fmt, &id) != WEO_OK) return 0;
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS) return 0;
+    return (size_t)nrhs * spinor_field_bytes(g, id);
+}
+
+int weo_pack_gauge(const weo_lattice* lat, const weo_format* fmt, const void* u_canon, int canon_prec,
+                   void* u_packed, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if (canon_prec != WEO_F64 && canon_prec != WEO_F32) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(u_canon));
+    WEO_TRY(check_ptr(u_packed));
+    const size_t nc = (size_t)g.vh * 2 * 4 * 9 * (canon_prec == WEO_F64 ? 16 : 8);
+    if (overlaps(u_canon, nc, u_packed, gauge_field_bytes(g, id))) return WEO_ERR_ARG;
+    return hip_status(launch_pack_gauge(g, id, u_canon, canon_prec == WEO_F64, u_packed,
+                                        static_cast<hipStream_t>(stream)));
+}
+
+int weo_pack_spinor(const weo_lattice* lat, const weo_format* fmt, int nrhs, const void* s_canon,
+                    int canon_prec, double scale, void* s_packed, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS || !std::isfinite(scale)) return WEO_ERR_ARG;
+    if (canon_prec != WEO_F64 && canon_prec != WEO_F32) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(s_canon));
+    WEO_TRY(check_ptr(s_packed));
+    const size_t nc = (size_t)nrhs * g.vh * 12 * (canon_prec == WEO_F64 ? 16 : 8);
+    if (overlaps(s_canon, nc, s_packed, (size_t)nrhs * spinor_field_bytes(g, id))) return WEO_ERR_ARG;
+    return hip_status(launch_pack_spinor(g, id, nrhs, s_canon, canon_prec == WEO_F64, scale, s_packed,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+int weo_unpack_spinor(const weo_lattice* lat, const weo_format* fmt, int nrhs, const void* s_packed,
+                      double scale, void* s_canon, int canon_prec, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS || !std::isfinite(scale)) return WEO_ERR_ARG;
+    if (canon_prec != WEO_F64 && canon_prec != WEO_F32) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(s_canon));
+    WEO_TRY(check_ptr(s_packed));
+    const size_t nc = (size_t)nrhs * g.vh * 12 * (canon_prec == WEO_F64 ? 16 : 8);
+    if (overlaps(s_canon, nc, s_packed, (size_t)nrhs * spinor_field_bytes(g, id))) return WEO_ERR_ARG;
+    return hip_status(launch_unpack_spinor(g, id, nrhs, s_packed, scale, s_canon, canon_prec == WEO_F64,
+                                           static_cast<hipStream_t>(stream)));
+}
+
+int wilson_eo_hop(const weo_lattice* lat, const weo_format* fmt, int out_parity, int dagger,
+                  const void* u, const void* in, void* out, int nrhs, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if ((out_parity != 0 && out_parity != 1) || (dagger != 0 && dagger != 1)) return WEO_ERR_ARG;
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(u));
+    WEO_TRY(check_ptr(in));
+    WEO_TRY(check_ptr(out));
+    const size_t sb = (size_t)nrhs * spinor_field_bytes(g, id);
+    if (overlaps(in, sb, out, sb) || overlaps(u, gauge_field_bytes(g, id), out, sb)) return WEO_ERR_ARG;
+    HopLaunch h;
+    h.g = g;
+    h.fmt = id;
+    h.out_par = out_parity;
+    h.dagger = dagger;
+    phases_of(lat, h.phase);
+    h.u = u;
+    h.in = in;
+    h.out = out;
+    h.y = nullptr;
+    h.alpha = 0.0;
+    h.partial = nullptr;
+    h.nrhs = nrhs;
+    return hip_status(launch_hop(h, static_cast<hipStream_t>(stream)));
+}
+
+int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger, const void* u,
+                    const void* in, void* out, void* tmp, int nrhs, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if (dagger != 0 && dagger != 1) return WEO_ERR_ARG;
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(u));
+    WEO_TRY(check_ptr(in));
+    WEO_TRY(check_ptr(out));
+    WEO_TRY(check_ptr(tmp));
+    const size_t sb = (size_t)nrhs * spinor_field_bytes(g, id);
+    const size_t gb = gauge_field_bytes(g, id);
+    if (overlaps(in, sb, out, sb) || overlaps(in, sb, tmp, sb) || overlaps(out, sb, tmp, sb) ||
+        overlaps(u, gb, out, sb) || overlaps(u, gb, tmp, sb))
+        return WEO_ERR_ARG;
+    HopLaunch h;
+    h.g = g;
+    h.fmt = id;
+    h.dagger = dagger;
+    phases_of(lat, h.phase);
+    h.u = u;
+    h.nrhs = nrhs;
+    h.partial = nullptr;
+    // tmp_o = H_oe in
+    h.out_par = 1;
+    h.in = in;
+    h.out = tmp;
+    h.y = nullptr;
+    h.alpha = 0.0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    WEO_TRY(hip_status(launch_hop(h, s)));
+    // out_e = in - kappa^2 H_eo tmp_o
+    h.out_par = 0;
+    h.in = tmp;
+    h.out = out;
+    h.y = in;
+    h.alpha = -lat->kappa * lat->kappa;
+    return hip_status(launch_hop(h, s));
+}
+
+}  // extern "C"

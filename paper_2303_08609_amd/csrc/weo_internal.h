@@ -1,0 +1,108 @@
+// Host-side interface between the C ABI / solver code (plain C++) and the HIP
+// translation units that own the kernels.  Nothing here is exported.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "weo_geom.h"
+
+namespace weo {
+
+// Per-format facts needed on the host.
+struct FmtInfo {
+    int spinor_prec, link_prec, link12;
+    int spinor_site_bytes;   // 12 complex
+    int link_bytes;          // 9 or 6 complex
+    int wide;                // 1 if arithmetic is FP64
+};
+const FmtInfo& fmt_info(int fmt_id);
+
+inline size_t spinor_field_bytes(const Geom& g, int fmt_id) {
+    return (size_t)g.vh * (size_t)fmt_info(fmt_id).spinor_site_bytes;
+}
+inline size_t gauge_block_bytes(const Geom& g, int fmt_id) {   // one (mu, parity) block
+    return (size_t)g.vh * (size_t)fmt_info(fmt_id).link_bytes;
+}
+inline size_t gauge_field_bytes(const Geom& g, int fmt_id) { return 8 * gauge_block_bytes(g, fmt_id); }
+
+// Epilogue of a hop launch: out = hop(in)               (y == nullptr)
+//                           out = y + alpha * hop(in)    (y != nullptr)
+// with optional per-workgroup partial sums of ||out||^2 (FP64) per rhs.
+struct HopLaunch {
+    Geom g;
+    int fmt;
+    int out_par;
+    int dagger;
+    double phase[4][2];
+    const void* u;
+    const void* in;
+    void* out;
+    const void* y;
+    double alpha;
+    double* partial;      // [nrhs][hop_blocks()] or nullptr
+    int nrhs;
+};
+
+struct TuneCfg {
+    int block;    // threads per workgroup (multiple of 64, <= 1024)
+    int remap;    // XCD-aware workgroup remap on/off
+    int rhs_grp;  // multi-rhs: rhs handled per thread (divides the tile)
+};
+TuneCfg& hop_tune();                       // current single-rhs launch shape
+uint32_t hop_blocks(const Geom& g, int nrhs);
+hipError_t launch_hop(const HopLaunch& h, hipStream_t s);
+
+// ---- BLAS-1 on packed spinor fields (one parity, nrhs fields) -------------
+// Scalars live in device memory (double) so the solver never needs the host
+// in the loop.  ``mask`` (may be null) is a per-rhs int array: rhs with
+// mask[r] == 0 are left untouched.
+uint32_t blas_blocks(const Geom& g);
+// partial[r][b] = sum over block b of |a|^2 (b_ == null) or Re<a, b_>
+hipError_t launch_norm2(const Geom& g, int fmt, const void* a, int nrhs,
+                        double* partial, hipStream_t s);
+// Deterministic final sum: out[r] = sum_b partial[r][b], fixed order.
+hipError_t launch_reduce(const double* partial, int nblocks, int nrhs,
+                         double* out, hipStream_t s);
+
+// CGLS / CG vector updates, per rhs r with device scalars:
+//   x += alpha_r p;  s -= alpha_r q            (cg_update_xs)
+//   p  = r + beta_r p                          (cg_update_p)
+hipError_t launch_axpy2(const Geom& g, int fmt, int nrhs,
+                        const double* alpha, const int* mask,
+                        void* x, const void* p, void* sv, const void* q,
+                        double* partial_s, hipStream_t s);
+hipError_t launch_xpay(const Geom& g, int fmt, int nrhs,
+                       const double* beta, const int* mask,
+                       const void* r, void* p, hipStream_t s);
+// out = a + c * b (c host scalar, FP64), any of the same-format fields
+hipError_t launch_axpby(const Geom& g, int fmt, int nrhs, double ca, const void* a,
+                        double cb, const void* b, void* out, double* partial,
+                        hipStream_t s);
+// copy / convert between formats with scaling: out = in * scale[r] (scale may
+// be null = 1), optionally accumulating (out += in * scale[r]).
+hipError_t launch_convert(const Geom& g, int fmt_in, const void* in, int fmt_out,
+                          void* out, int nrhs, const double* scale, int accumulate,
+                          hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// Solver scalar kernels (single workgroup): see solver.cpp for the formulas.
+hipError_t launch_cg_scalars(int kind, int nrhs, double* sc, const double* red,
+                             int* mask, int* flags, double tol2, hipStream_t s);
+
+// ---- pack / unpack --------------------------------------------------------
+hipError_t launch_pack_gauge(const Geom& g, int fmt, const void* canon, int canon_f64,
+                             void* packed, hipStream_t s);
+hipError_t launch_pack_spinor(const Geom& g, int fmt, int nrhs, const void* canon,
+                              int canon_f64, double scale, void* packed, hipStream_t s);
+hipError_t launch_unpack_spinor(const Geom& g, int fmt, int nrhs, const void* packed,
+                                double scale, void* canon, int canon_f64, hipStream_t s);
+
+// ---- force ------------------------------------------------------------------
+hipError_t launch_force(const Geom& g, int fmt, const double phase[4][2], const void* u,
+                        const void* lam_e, const void* lam_o, const void* r_e,
+                        const void* r_o, double coeff, int project, void* g_canon,
+                        int canon_f64, hipStream_t s);
+
+}  // namespace weo

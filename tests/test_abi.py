@@ -1,0 +1,108 @@
+"""The C ABI library without a GPU: it loads, exports every function the
+header declares, passes its host-side index self-test, and rejects bad
+arguments before making any HIP call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2303_08609_amd import wilson_eo as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "wilson_eo.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+def test_header_functions_are_exported_and_bound():
+    lib = W.load()
+    names = _declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in W.exported_names(), f"{n} not bound in wilson_eo.py"
+
+
+def test_selftest():
+    assert W.weo_selftest() == 0
+
+
+def test_strerror():
+    for code in (0, -1, -2, -3, -4, -5, -6, 1, 2):
+        assert W.strerror(code) and W.strerror(code) != "unknown status code"
+    assert W.strerror(-99) == "unknown status code"
+
+
+def test_sizes():
+    lat = W.make_lattice((32, 32, 32, 64), 0.126)
+    f32 = W.make_format(W.WEO_F32, W.WEO_F32, W.WEO_LINK18)
+    f32c = W.make_format(W.WEO_F32, W.WEO_F32, W.WEO_LINK12)
+    f64 = W.make_format(W.WEO_F64)
+    vh = 32 ** 3 * 64 // 2
+    assert W.weo_gauge_bytes(lat, f32) == 8 * vh * 72
+    assert W.weo_gauge_bytes(lat, f32c) == 8 * vh * 48
+    assert W.weo_spinor_bytes(lat, f32, 1) == vh * 96
+    assert W.weo_spinor_bytes(lat, f64, 12) == 12 * vh * 192
+    hh = W.make_format(W.WEO_BF16, W.WEO_F16, W.WEO_LINK12)
+    assert W.weo_format_supported(hh) == 1
+    assert W.weo_gauge_bytes(lat, hh) == 8 * vh * 24
+    assert W.weo_spinor_bytes(lat, hh, 1) == vh * 48
+
+
+def test_unsupported_and_bad_formats():
+    lat = W.make_lattice((4, 4, 4, 4), 0.1)
+    assert W.weo_format_supported(W.make_format(W.WEO_F32, W.WEO_F64)) == 0
+    assert W.weo_gauge_bytes(lat, W.make_format(W.WEO_F32, W.WEO_F64)) == 0
+    bad = W.make_format(7, 0, 0)
+    assert W.weo_spinor_bytes(lat, bad, 1) == 0
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 4, 4), (4, 4, 4, 0), (4, -2, 4, 4), (1, 1, 1, 1),
+                                  (4096, 4096, 4096, 4096)])
+def test_bad_dims(dims):
+    lat = W.make_lattice(dims, 0.1)
+    f = W.make_format(W.WEO_F32)
+    assert W.weo_spinor_bytes(lat, f, 1) == 0
+    rc = W.wilson_eo_apply(lat, f, 0, 256, 512, 1024, 2048, 1, None)
+    assert rc == W.WEO_ERR_DIMS
+
+
+def test_argument_validation_without_gpu():
+    lat = W.make_lattice((4, 4, 4, 4), 0.1)
+    f = W.make_format(W.WEO_F32)
+    a, b, c, d = 1 << 20, 2 << 20, 3 << 20, 4 << 20     # fake aligned, disjoint
+    # null and misaligned pointers
+    assert W.wilson_eo_apply(lat, f, 0, None, b, c, d, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_apply(lat, f, 0, a + 8, b, c, d, 1, None) == W.WEO_ERR_ALIGN
+    # bad flags and counts
+    assert W.wilson_eo_apply(lat, f, 2, a, b, c, d, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_apply(lat, f, 0, a, b, c, d, 0, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_apply(lat, f, 0, a, b, c, d, W.WEO_MAX_RHS + 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_hop(lat, f, 2, 0, a, b, c, 1, None) == W.WEO_ERR_ARG
+    # overlapping in/out
+    assert W.wilson_eo_hop(lat, f, 1, 0, a, b, b + 256, 1, None) == W.WEO_ERR_ARG
+    # unsupported combination and unknown enum
+    assert W.wilson_eo_hop(lat, W.make_format(W.WEO_F32, W.WEO_F64), 1, 0, a, b, c, 1,
+                           None) == W.WEO_ERR_FORMAT
+    assert W.wilson_eo_hop(lat, W.make_format(9), 1, 0, a, b, c, 1, None) == W.WEO_ERR_ARG
+    # null lattice / format
+    assert W.wilson_eo_hop(None, f, 1, 0, a, b, c, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_hop(lat, None, 1, 0, a, b, c, 1, None) == W.WEO_ERR_ARG
+    # non-finite kappa or phase
+    lat_nan = W.make_lattice((4, 4, 4, 4), float("nan"))
+    assert W.wilson_eo_apply(lat_nan, f, 0, a, b, c, d, 1, None) == W.WEO_ERR_ARG
+    # pack: bad canonical precision, bad scale
+    assert W.weo_pack_spinor(lat, f, 1, a, 5, 1.0, b, None) == W.WEO_ERR_ARG
+    assert W.weo_pack_spinor(lat, f, 1, a, 0, float("inf"), b, None) == W.WEO_ERR_ARG
+    assert W.weo_pack_gauge(lat, f, a, 0, None, None) == W.WEO_ERR_ARG
+
+
+def test_python_raises_on_error_codes():
+    with pytest.raises(W.WilsonEOError):
+        W.check(W.WEO_ERR_ARG, "x")
+    assert W.check(W.WEO_NOT_CONVERGED, "x") == W.WEO_NOT_CONVERGED
