@@ -187,21 +187,26 @@ int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt,
                  weo_solver_info* info, void* stream);
 
 /* ---- derivatives --------------------------------------------------------- */
+#define WEO_FORCE_PROJECT     1   /* write F = TH(i U g^dag) instead of g */
+#define WEO_FORCE_ACCUMULATE  2   /* add to g_canon instead of overwriting it */
+
 /* Link gradient of coeff * Re <Lambda, H R> for full-lattice fields given as
  * even and odd packed parts (1 rhs each).  For the link U_mu(x) with boundary
  * phase b (bc[mu] where x_mu = L_mu - 1, else 1):
  *   g = coeff * conj(b) * [ sum_s ((1-gamma_mu) Lambda(x))_s R(x+mu)_s^dag
  *                         + sum_s R(x)_s ((1+gamma_mu) Lambda(x+mu))_s^dag ]
- * which is d/dU in the convention dL = Re tr(g^dag dU).  With project = 1 the
- * su(3) force F = TH(i U g^dag) is written instead (TH = traceless Hermitian
- * part), so that dL/d eps = tr(X F) for U -> exp(i eps X) U.
+ * which is the gradient in the convention dL = Re tr(g^dag dU).  With
+ * WEO_FORCE_PROJECT the su(3) force F = TH(i U g^dag) is written instead
+ * (TH = traceless Hermitian part), so that dL/d eps = tr(X F) for
+ * U -> exp(i eps X) U.  The derivation follows from Eq. (1) and Eq. (4).
  * For L = Re<eta, M psi>: Lambda = (eta, H_eo^dag eta), R = (psi, H_oe psi),
- * coeff = -kappa^2.  Output: canonical gauge layout in canon_prec. */
+ * coeff = -kappa^2.  Output: canonical gauge layout in canon_prec; the
+ * gradient is accumulated in FP64.  flags: WEO_FORCE_* bits. */
 int wilson_eo_force(const weo_lattice* lat, const weo_format* fmt,
                     const void* u,
                     const void* lam_e, const void* lam_o,
                     const void* r_e, const void* r_o,
-                    double coeff, int project,
+                    double coeff, int flags,
                     void* g_canon, int canon_prec, void* stream);
 
 #ifdef __cplusplus

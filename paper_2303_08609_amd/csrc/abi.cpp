@@ -246,4 +246,25 @@ int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger, c
     return hip_status(launch_hop(h, s));
 }
 
+int wilson_eo_force(const weo_lattice* lat, const weo_format* fmt, const void* u, const void* lam_e,
+                    const void* lam_o, const void* r_e, const void* r_o, double coeff, int flags,
+                    void* g_canon, int canon_prec, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if ((flags & ~(WEO_FORCE_PROJECT | WEO_FORCE_ACCUMULATE)) || !std::isfinite(coeff)) return WEO_ERR_ARG;
+    if (canon_prec != WEO_F64 && canon_prec != WEO_F32) return WEO_ERR_ARG;
+    const void* ptrs[6] = {u, lam_e, lam_o, r_e, r_o, g_canon};
+    for (const void* q : ptrs) WEO_TRY(check_ptr(q));
+    const size_t ob = (size_t)g.vh * 2 * 4 * 9 * (canon_prec == WEO_F64 ? 16 : 8);
+    const size_t sb = spinor_field_bytes(g, id);
+    for (int i = 0; i < 5; ++i)
+        if (overlaps(ptrs[i], i == 0 ? gauge_field_bytes(g, id) : sb, g_canon, ob)) return WEO_ERR_ARG;
+    double ph[4][2];
+    phases_of(lat, ph);
+    return hip_status(launch_force(g, id, ph, u, lam_e, lam_o, r_e, r_o, coeff, flags, g_canon,
+                                   canon_prec == WEO_F64, static_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

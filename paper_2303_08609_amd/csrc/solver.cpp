@@ -1,0 +1,447 @@
+// Krylov solvers for the even-odd system (host driver; all vector work runs in
+// the library's kernels, scalars stay on the device).
+//
+// The paper (Sec. 2) only states that iterative solvers dominate and that
+// their cost is the matrix multiplication; the algorithms are standard:
+//
+//  CGLS for M x = b (CG on M^dag M x = M^dag b, carrying s = b - M x):
+//     s = b - M x;  r = M^dag s;  p = r;  gamma = <r, r>
+//     repeat: q = M p;  alpha = gamma / ||q||^2;  x += alpha p;  s -= alpha q;
+//             r = M^dag s;  beta = <r, r> / gamma;  gamma = <r, r>;  p = r + beta p
+//  CG for M^dag M x = b:
+//     r = b - A x;  p = r;  gamma = <r, r>
+//     repeat: t = M p;  q = M^dag t;  alpha = gamma / ||t||^2;  x += alpha p;
+//             r -= alpha q;  beta = <r, r> / gamma;  gamma = <r, r>;  p = r + beta p
+//  Defect correction (mixed precision): in FP64, r = b - A x; the residual is
+//  rescaled to unit RMS component, solved approximately in the inner format
+//  (relative tolerance inner_tol) and the correction added back in FP64.
+//
+// "acc" is the format of the iterate x and residual s (r for CG); "op" the
+// format of every vector the operator reads or writes (p, q, r, t).  Norms
+// and dot products accumulate in FP64 in every format.  The host looks at the
+// residual norms every check_every iterations (one small copy and one stream
+// synchronisation); nothing else leaves the device.
+#include <hip/hip_runtime_api.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/wilson_eo.h"
+#include "weo_internal.h"
+
+namespace weo {
+
+int check_lattice(const weo_lattice* lat, Geom* g);
+int check_fmt(const weo_format* f, int* id);
+int check_ptr(const void* p);
+bool overlaps(const void* a, size_t na, const void* b, size_t nb);
+void phases_of(const weo_lattice* lat, double ph[4][2]);
+
+namespace {
+
+#define HIPCHK(expr)                                  \
+    do {                                              \
+        if ((expr) != hipSuccess) return WEO_ERR_HIP; \
+    } while (0)
+
+struct Carve {
+    uint8_t* base;
+    size_t size, off;
+    void* take(size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        void* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+// Device scalar block: one entry per rhs for each quantity.
+struct Scalars {
+    double *gamma, *alpha, *beta, *ss, *bb, *rr, *sc_in, *sc_out, *nrm;
+    int *mask, *flags;
+};
+
+struct Workspace {
+    // fields (nrhs each)
+    void *s_acc, *x_acc, *s_op, *p, *q, *r, *t, *tmp;     // level vectors
+    void *r64, *t64, *tmp64;                              // outer (mixed) vectors
+    double *pa, *pb, *pc;                                 // partial sums
+    Scalars sc;
+    size_t bytes;
+};
+
+// The format used for FP32 accumulation vectors (spinor part only matters).
+constexpr int kAccF32 = FMT_S_S_18;
+
+uint32_t max_partials(const Geom& g) {
+    const uint32_t a = (g.vh + 63) / 64;           // smallest legal hop workgroup
+    const uint32_t b = blas_blocks(g);
+    return a > b ? a : b;
+}
+
+Workspace carve_ws(const Geom& g, int fmt, const weo_solver_params* p, int inner_fmt, uint8_t* base,
+                   size_t size) {
+    Carve c{base, size, 0};
+    Workspace w;
+    std::memset(&w, 0, sizeof(w));
+    const int n = p->nrhs;
+    const int op = p->mixed ? inner_fmt : fmt;
+    const int acc = p->mixed ? kAccF32 : fmt;
+    const size_t fo = (size_t)n * spinor_field_bytes(g, op);
+    const size_t fa = (size_t)n * spinor_field_bytes(g, acc);
+    w.s_acc = c.take(fa);
+    if (p->mixed) w.x_acc = c.take(fa);
+    if (fmt_info(acc).spinor_prec != fmt_info(op).spinor_prec) w.s_op = c.take(fo);
+    w.p = c.take(fo);
+    w.q = c.take(fo);
+    w.r = c.take(fo);
+    w.t = c.take(fo);
+    w.tmp = c.take(fo);
+    if (p->mixed) {
+        const size_t f64 = (size_t)n * spinor_field_bytes(g, fmt);
+        w.r64 = c.take(f64);
+        w.t64 = c.take(f64);
+        w.tmp64 = c.take(f64);
+    }
+    const size_t np = (size_t)n * max_partials(g) * sizeof(double);
+    w.pa = static_cast<double*>(c.take(np));
+    w.pb = static_cast<double*>(c.take(np));
+    w.pc = static_cast<double*>(c.take(np));
+    double* d = static_cast<double*>(c.take(9 * WEO_MAX_RHS * sizeof(double)));
+    int* ip = static_cast<int*>(c.take(2 * WEO_MAX_RHS * sizeof(int)));
+    if (d) {
+        w.sc.gamma = d; w.sc.alpha = d + 16; w.sc.beta = d + 32; w.sc.ss = d + 48; w.sc.bb = d + 64;
+        w.sc.rr = d + 80; w.sc.sc_in = d + 96; w.sc.sc_out = d + 112; w.sc.nrm = d + 128;
+        w.sc.mask = ip; w.sc.flags = ip + 16;
+    }
+    w.bytes = c.off;
+    return w;
+}
+
+struct Ctx {
+    const weo_lattice* lat;
+    Geom g;
+    double ph[4][2];
+    hipStream_t st;
+    int applies;
+};
+
+// out = A in with A = M (dagger 0) or M^dag (dagger 1); partial = ||out||^2.
+hipError_t apply_m(Ctx& c, int fmt, const void* u, int dagger, const void* in, void* out, void* tmp,
+                   int nrhs, double* partial) {
+    HopLaunch h;
+    h.g = c.g;
+    h.fmt = fmt;
+    h.dagger = dagger;
+    std::memcpy(h.phase, c.ph, sizeof(h.phase));
+    h.u = u;
+    h.nrhs = nrhs;
+    h.out_par = 1;
+    h.in = in;
+    h.out = tmp;
+    h.y = nullptr;
+    h.alpha = 0.0;
+    h.partial = nullptr;
+    hipError_t e = launch_hop(h, c.st);
+    if (e != hipSuccess) return e;
+    h.out_par = 0;
+    h.in = tmp;
+    h.out = out;
+    h.y = in;
+    h.alpha = -c.lat->kappa * c.lat->kappa;
+    h.partial = partial;
+    ++c.applies;
+    return launch_hop(h, c.st);
+}
+
+// out = A x for the solver operator (M, or M^dag M through mid); partial = ||out||^2
+// (for M^dag M the partial holds ||M x||^2 only when want_mid_norm).
+hipError_t apply_op(Ctx& c, int op, int fmt, const void* u, const void* x, void* out, void* mid, void* tmp,
+                    int nrhs, double* partial) {
+    if (op == WEO_OP_M) return apply_m(c, fmt, u, 0, x, out, tmp, nrhs, partial);
+    hipError_t e = apply_m(c, fmt, u, 0, x, mid, tmp, nrhs, partial);
+    if (e != hipSuccess) return e;
+    return apply_m(c, fmt, u, 1, mid, out, tmp, nrhs, nullptr);
+}
+
+ScalarArgsHost sargs(const Scalars& s, int nrhs) {
+    ScalarArgsHost a;
+    std::memset(&a, 0, sizeof(a));
+    a.nrhs = nrhs;
+    a.gamma = s.gamma; a.alpha = s.alpha; a.beta = s.beta; a.ss = s.ss;
+    a.mask = s.mask; a.flags = s.flags; a.sc_in = s.sc_in; a.sc_out = s.sc_out; a.nrm = s.nrm;
+    return a;
+}
+
+struct LevelResult {
+    int iters;
+    int breakdown;
+};
+
+// Iterate one precision level.  On entry: x_acc holds the start (zero or x0),
+// s_acc the matching residual (b - M x for CGLS, b - A x for CG), mask the
+// live rhs, bb[r] = ||b||^2.  Stops per rhs when ||s||^2 <= tol^2 bb.
+int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const void* u, void* x_acc,
+              int nrhs, double tol, int maxiter, int check_every, LevelResult* res) {
+    const Geom& g = c.g;
+    // the residual doubles as the operator input when both are stored alike
+    const bool same = fmt_info(fmt_op).spinor_prec == fmt_info(fmt_acc).spinor_prec;
+    void* s_op = same ? w.s_acc : w.s_op;
+    const uint32_t nbh = hop_blocks(g, nrhs), nbb = blas_blocks(g);
+    ScalarArgsHost sa = sargs(w.sc, nrhs);
+    res->iters = 0;
+    res->breakdown = 0;
+    if (!same) HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_op, s_op, nrhs, nullptr, 0, c.st));
+    if (op == WEO_OP_M) {
+        // r = M^dag s, gamma = ||r||^2, p = r
+        HIPCHK(apply_m(c, fmt_op, u, 1, s_op, w.r, w.tmp, nrhs, w.pa));
+    } else {
+        HIPCHK(launch_norm2(g, fmt_op, s_op, nrhs, w.pa, c.st));
+        HIPCHK(launch_convert(g, fmt_op, s_op, fmt_op, w.r, nrhs, nullptr, 0, c.st));
+    }
+    HIPCHK(launch_reduce(w.pa, op == WEO_OP_M ? (int)nbh : (int)nbb, nrhs, w.sc.gamma, c.st));
+    HIPCHK(launch_convert(g, fmt_op, w.r, fmt_op, w.p, nrhs, nullptr, 0, c.st));
+
+    std::vector<double> ss(nrhs), bb(nrhs);
+    std::vector<int> mask(nrhs), flags(nrhs);
+    const double tol2 = tol * tol;
+    // a start that already meets the tolerance costs no iteration
+    HIPCHK(launch_norm2(g, fmt_acc, w.s_acc, nrhs, w.pb, c.st));
+    HIPCHK(launch_reduce(w.pb, (int)nbb, nrhs, w.sc.ss, c.st));
+    HIPCHK(hipMemcpyAsync(ss.data(), w.sc.ss, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(bb.data(), w.sc.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(mask.data(), w.sc.mask, nrhs * sizeof(int), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    {
+        int live = 0;
+        for (int r = 0; r < nrhs; ++r) {
+            if (mask[r] && ss[r] <= tol2 * bb[r]) mask[r] = 0;
+            live += mask[r] != 0;
+        }
+        HIPCHK(hipMemcpyAsync(w.sc.mask, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        if (!live) return WEO_OK;
+    }
+    for (int it = 1; it <= maxiter; ++it) {
+        // q = A p with the alpha denominator in pa
+        if (op == WEO_OP_M) {
+            HIPCHK(apply_m(c, fmt_op, u, 0, w.p, w.q, w.tmp, nrhs, w.pa));
+        } else {
+            HIPCHK(apply_op(c, op, fmt_op, u, w.p, w.q, w.t, w.tmp, nrhs, w.pa));
+        }
+        sa.pa = w.pa; sa.nba = (int)nbh; sa.pb = nullptr; sa.nbb = 0;
+        HIPCHK(launch_scalars(SCAL_ALPHA, sa, c.st));
+        // x += alpha p; s -= alpha q (s is the CG residual r for M^dag M)
+        HIPCHK(launch_axpy2(g, fmt_acc, fmt_op, nrhs, w.sc.alpha, w.sc.mask, x_acc, w.p, w.s_acc, w.q,
+                            same ? nullptr : s_op, w.pb, c.st));
+        if (op == WEO_OP_M) {
+            HIPCHK(apply_m(c, fmt_op, u, 1, s_op, w.r, w.tmp, nrhs, w.pc));
+            sa.pa = w.pc; sa.nba = (int)nbh; sa.pb = w.pb; sa.nbb = (int)nbb;
+            HIPCHK(launch_scalars(SCAL_BETA, sa, c.st));
+            HIPCHK(launch_xpay(g, fmt_op, nrhs, w.sc.beta, w.sc.mask, w.r, w.p, c.st));
+        } else {
+            sa.pa = w.pb; sa.nba = (int)nbb; sa.pb = nullptr; sa.nbb = 0;
+            HIPCHK(launch_scalars(SCAL_BETA, sa, c.st));
+            HIPCHK(launch_xpay(g, fmt_op, nrhs, w.sc.beta, w.sc.mask, s_op, w.p, c.st));
+        }
+        res->iters = it;
+        if (it % check_every == 0 || it == maxiter) {
+            HIPCHK(hipMemcpyAsync(ss.data(), w.sc.ss, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+            HIPCHK(hipMemcpyAsync(mask.data(), w.sc.mask, nrhs * sizeof(int), hipMemcpyDeviceToHost, c.st));
+            HIPCHK(hipMemcpyAsync(flags.data(), w.sc.flags, nrhs * sizeof(int), hipMemcpyDeviceToHost, c.st));
+            HIPCHK(hipStreamSynchronize(c.st));
+            int live = 0;
+            bool changed = false;
+            for (int r = 0; r < nrhs; ++r) {
+                if (flags[r]) res->breakdown = 1;
+                if (mask[r] && ss[r] <= tol2 * bb[r]) { mask[r] = 0; changed = true; }
+                live += mask[r] != 0;
+            }
+            if (changed)
+                HIPCHK(hipMemcpyAsync(w.sc.mask, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c.st));
+            if (!live) break;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(c.st));
+    return WEO_OK;
+}
+
+// True relative residuals ||b - A x|| / ||b|| in format fmt (x, b in fmt).
+int true_resid(Ctx& c, const Workspace& w, int op, int fmt, const void* u, const void* b, const void* x,
+               void* t, void* mid, void* tmp, int nrhs, double* out) {
+    const Geom& g = c.g;
+    HIPCHK(apply_op(c, op, fmt, u, x, t, mid, tmp, nrhs, nullptr));
+    HIPCHK(launch_axpby(g, fmt, nrhs, 1.0, b, -1.0, t, t, w.pa, c.st));
+    HIPCHK(launch_reduce(w.pa, (int)blas_blocks(g), nrhs, w.sc.rr, c.st));
+    std::vector<double> rr(nrhs), bb(nrhs);
+    HIPCHK(hipMemcpyAsync(rr.data(), w.sc.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(bb.data(), w.sc.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    for (int r = 0; r < nrhs; ++r) out[r] = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : std::sqrt(rr[r]);
+    return WEO_OK;
+}
+
+int set_mask(Ctx& c, const Workspace& w, const std::vector<int>& mask) {
+    std::vector<int> zero(mask.size(), 0);
+    HIPCHK(hipMemcpyAsync(w.sc.mask, mask.data(), mask.size() * sizeof(int), hipMemcpyHostToDevice, c.st));
+    HIPCHK(hipMemcpyAsync(w.sc.flags, zero.data(), zero.size() * sizeof(int), hipMemcpyHostToDevice, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));   // host vectors go out of scope
+    return WEO_OK;
+}
+
+int check_params(const weo_solver_params* p, int fmt, int* inner_fmt) {
+    if (!p) return WEO_ERR_ARG;
+    if (p->op != WEO_OP_M && p->op != WEO_OP_MDAGM) return WEO_ERR_ARG;
+    if (p->nrhs < 1 || p->nrhs > WEO_MAX_RHS) return WEO_ERR_ARG;
+    if (!(p->tol > 0.0) || !std::isfinite(p->tol) || p->maxiter < 0) return WEO_ERR_ARG;
+    if (p->check_every < 1 || (p->x0_given != 0 && p->x0_given != 1)) return WEO_ERR_ARG;
+    if (p->mixed != 0 && p->mixed != 1) return WEO_ERR_ARG;
+    *inner_fmt = fmt;
+    if (p->mixed) {
+        if (fmt_info(fmt).spinor_prec != WEO_F64) return WEO_ERR_FORMAT;
+        const int rc = check_fmt(&p->inner, inner_fmt);
+        if (rc != WEO_OK) return rc;
+        const int sp = fmt_info(*inner_fmt).spinor_prec;
+        if (sp == WEO_F64) return WEO_ERR_FORMAT;
+        if (!(p->inner_tol > 0.0) || !(p->inner_tol < 1.0) || p->max_outer < 1) return WEO_ERR_ARG;
+    } else {
+        // a plain solve accumulates in its own format; FP16/BF16 storage is
+        // only used as the inner format of a mixed solve
+        const int sp = fmt_info(fmt).spinor_prec;
+        if (sp != WEO_F64 && sp != WEO_F32) return WEO_ERR_FORMAT;
+    }
+    return WEO_OK;
+}
+
+}  // namespace
+}  // namespace weo
+
+using namespace weo;
+
+extern "C" size_t wilson_eo_cg_workspace_bytes(const weo_lattice* lat, const weo_format* fmt,
+                                               const weo_solver_params* p) {
+    Geom g;
+    int id, inner;
+    if (check_lattice(lat, &g) != WEO_OK || check_fmt(fmt, &id) != WEO_OK) return 0;
+    if (check_params(p, id, &inner) != WEO_OK) return 0;
+    return carve_ws(g, id, p, inner, nullptr, 0).bytes;
+}
+
+extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const weo_solver_params* p,
+                            const void* u, const void* u_inner, const void* b, void* x, void* workspace,
+                            size_t ws_bytes, weo_solver_info* info, void* stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    Geom g;
+    int id, inner;
+    int rc;
+    if ((rc = check_lattice(lat, &g)) != WEO_OK) return rc;
+    if ((rc = check_fmt(fmt, &id)) != WEO_OK) return rc;
+    if ((rc = check_params(p, id, &inner)) != WEO_OK) return rc;
+    if (!info) return WEO_ERR_ARG;
+    if ((rc = check_ptr(u)) != WEO_OK || (rc = check_ptr(b)) != WEO_OK || (rc = check_ptr(x)) != WEO_OK)
+        return rc;
+    if (p->mixed && (rc = check_ptr(u_inner)) != WEO_OK) return rc;
+    if ((rc = check_ptr(workspace)) != WEO_OK) return rc == WEO_ERR_ARG ? WEO_ERR_WORKSPACE : rc;
+    const Workspace need = carve_ws(g, id, p, inner, nullptr, 0);
+    if (ws_bytes < need.bytes) return WEO_ERR_WORKSPACE;
+    const int n = p->nrhs;
+    const size_t fb = (size_t)n * spinor_field_bytes(g, id);
+    if (overlaps(b, fb, x, fb) || overlaps(workspace, ws_bytes, x, fb) || overlaps(workspace, ws_bytes, b, fb))
+        return WEO_ERR_ARG;
+
+    std::memset(info, 0, sizeof(*info));
+    Workspace w = carve_ws(g, id, p, inner, static_cast<uint8_t*>(workspace), ws_bytes);
+    Ctx c;
+    c.lat = lat;
+    c.g = g;
+    phases_of(lat, c.ph);
+    c.st = static_cast<hipStream_t>(stream);
+    c.applies = 0;
+    const uint32_t nbb = blas_blocks(g);
+    std::vector<int> live(n, 1);
+    int status = WEO_OK;
+
+    // bb = ||b||^2
+    HIPCHK(launch_norm2(g, id, b, n, w.pa, c.st));
+    HIPCHK(launch_reduce(w.pa, (int)nbb, n, w.sc.bb, c.st));
+
+    if (!p->mixed) {
+        // s = b - A x (or b), x = 0 when no start is given
+        if (p->x0_given) {
+            HIPCHK(apply_op(c, p->op, id, u, x, w.q, w.t, w.tmp, n, nullptr));
+            HIPCHK(launch_axpby(g, id, n, 1.0, b, -1.0, w.q, w.s_acc, nullptr, c.st));
+        } else {
+            HIPCHK(launch_zero(x, fb, c.st));
+            HIPCHK(launch_convert(g, id, b, id, w.s_acc, n, nullptr, 0, c.st));
+        }
+        if ((rc = set_mask(c, w, live)) != WEO_OK) return rc;
+        LevelResult lr;
+        if ((rc = run_level(c, w, p->op, id, id, u, x, n, p->tol, p->maxiter, p->check_every, &lr)) != WEO_OK)
+            return rc;
+        info->iters = lr.iters;
+        if ((rc = true_resid(c, w, p->op, id, u, b, x, w.q, w.t, w.tmp, n, info->true_rel_resid)) != WEO_OK)
+            return rc;
+        for (int r = 0; r < n; ++r)
+            if (!(info->true_rel_resid[r] <= p->tol)) status = WEO_NOT_CONVERGED;
+        if (lr.breakdown) status = WEO_BREAKDOWN;
+    } else {
+        // FP64 defect correction around inner solves in the inner format.
+        const double target = 12.0 * (double)g.vh;    // unit RMS per complex component
+        if (!p->x0_given) HIPCHK(launch_zero(x, fb, c.st));
+        int inner_iters = 0, k = 0;
+        bool breakdown = false;
+        std::vector<double> rel(n);
+        for (;;) {
+            // r64 = b - A x; rr = ||r64||^2
+            HIPCHK(apply_op(c, p->op, id, u, x, w.t64, w.r64, w.tmp64, n, nullptr));
+            HIPCHK(launch_axpby(g, id, n, 1.0, b, -1.0, w.t64, w.r64, w.pa, c.st));
+            ScalarArgsHost sa = sargs(w.sc, n);
+            sa.pa = w.pa; sa.nba = (int)nbb; sa.target = target;
+            HIPCHK(launch_scalars(SCAL_SCALE, sa, c.st));
+            std::vector<double> rr(n), bb(n);
+            HIPCHK(hipMemcpyAsync(rr.data(), w.sc.nrm, n * sizeof(double), hipMemcpyDeviceToHost, c.st));
+            HIPCHK(hipMemcpyAsync(bb.data(), w.sc.bb, n * sizeof(double), hipMemcpyDeviceToHost, c.st));
+            HIPCHK(hipStreamSynchronize(c.st));
+            int nlive = 0;
+            for (int r = 0; r < n; ++r) {
+                rel[r] = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : std::sqrt(rr[r]);
+                live[r] = !(rel[r] <= p->tol);
+                nlive += live[r];
+            }
+            if (!nlive || k >= p->max_outer || inner_iters >= p->maxiter || breakdown) break;
+            // inner right-hand side: r64 scaled to unit RMS, in FP32; x_acc = 0
+            HIPCHK(launch_convert(g, id, w.r64, kAccF32, w.s_acc, n, w.sc.sc_in, 0, c.st));
+            HIPCHK(launch_zero(w.x_acc, (size_t)n * spinor_field_bytes(g, kAccF32), c.st));
+            // the inner stopping test compares with ||rhs||^2 = target
+            std::vector<double> tg(n, target);
+            HIPCHK(hipMemcpyAsync(w.sc.bb, tg.data(), n * sizeof(double), hipMemcpyHostToDevice, c.st));
+            if ((rc = set_mask(c, w, live)) != WEO_OK) return rc;
+            LevelResult lr;
+            if ((rc = run_level(c, w, p->op, inner, kAccF32, u_inner, w.x_acc, n, p->inner_tol,
+                                p->maxiter - inner_iters, p->check_every, &lr)) != WEO_OK)
+                return rc;
+            inner_iters += lr.iters;
+            breakdown = breakdown || lr.breakdown;
+            // x += x_acc * sc_out (only live rhs changed: x_acc = 0 elsewhere)
+            HIPCHK(launch_convert(g, kAccF32, w.x_acc, id, x, n, w.sc.sc_out, 1, c.st));
+            // restore ||b||^2
+            HIPCHK(launch_norm2(g, id, b, n, w.pa, c.st));
+            HIPCHK(launch_reduce(w.pa, (int)nbb, n, w.sc.bb, c.st));
+            ++k;
+        }
+        info->iters = inner_iters;
+        info->outer_iters = k;
+        for (int r = 0; r < n; ++r) {
+            info->true_rel_resid[r] = rel[r];
+            if (!(rel[r] <= p->tol)) status = WEO_NOT_CONVERGED;
+        }
+        if (breakdown && status != WEO_OK) status = WEO_BREAKDOWN;
+    }
+    info->applies = c.applies;
+    info->status = status;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}

@@ -57,39 +57,56 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s);
 // ---- BLAS-1 on packed spinor fields (one parity, nrhs fields) -------------
 // Scalars live in device memory (double) so the solver never needs the host
 // in the loop.  ``mask`` (may be null) is a per-rhs int array: rhs with
-// mask[r] == 0 are left untouched.
+// mask[r] == 0 are left untouched.  Partial sums are [nrhs][blas_blocks()].
 uint32_t blas_blocks(const Geom& g);
-// partial[r][b] = sum over block b of |a|^2 (b_ == null) or Re<a, b_>
 hipError_t launch_norm2(const Geom& g, int fmt, const void* a, int nrhs,
                         double* partial, hipStream_t s);
 // Deterministic final sum: out[r] = sum_b partial[r][b], fixed order.
 hipError_t launch_reduce(const double* partial, int nblocks, int nrhs,
                          double* out, hipStream_t s);
-
-// CGLS / CG vector updates, per rhs r with device scalars:
-//   x += alpha_r p;  s -= alpha_r q            (cg_update_xs)
-//   p  = r + beta_r p                          (cg_update_p)
-hipError_t launch_axpy2(const Geom& g, int fmt, int nrhs,
+// x += alpha_r p; s -= alpha_r q; s_op = s (when the formats differ);
+// partial_s = ||s||^2.  x, s in fmt_acc; p, q, s_op in fmt_op.
+hipError_t launch_axpy2(const Geom& g, int fmt_acc, int fmt_op, int nrhs,
                         const double* alpha, const int* mask,
-                        void* x, const void* p, void* sv, const void* q,
-                        double* partial_s, hipStream_t s);
+                        void* x, const void* p, void* s, const void* q, void* s_op,
+                        double* partial_s, hipStream_t st);
+// p = r + beta_r p
 hipError_t launch_xpay(const Geom& g, int fmt, int nrhs,
                        const double* beta, const int* mask,
                        const void* r, void* p, hipStream_t s);
-// out = a + c * b (c host scalar, FP64), any of the same-format fields
+// out = ca a + cb b (b may be null), optional partial ||out||^2
 hipError_t launch_axpby(const Geom& g, int fmt, int nrhs, double ca, const void* a,
                         double cb, const void* b, void* out, double* partial,
                         hipStream_t s);
-// copy / convert between formats with scaling: out = in * scale[r] (scale may
-// be null = 1), optionally accumulating (out += in * scale[r]).
+// out (fmt_out) = in (fmt_in) * scale[r] (scale may be null = 1) [+ out]
 hipError_t launch_convert(const Geom& g, int fmt_in, const void* in, int fmt_out,
                           void* out, int nrhs, const double* scale, int accumulate,
                           hipStream_t s);
+// clear bytes (a multiple of 16) with a kernel (safe inside graph capture)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
-// Solver scalar kernels (single workgroup): see solver.cpp for the formulas.
-hipError_t launch_cg_scalars(int kind, int nrhs, double* sc, const double* red,
-                             int* mask, int* flags, double tol2, hipStream_t s);
+// Solver scalar steps, one workgroup per rhs:
+//   SCAL_ALPHA: a = sum pa;  alpha = gamma / a (breakdown if a <= 0 or not finite)
+//   SCAL_BETA:  a = sum pa, b = sum pb;  beta = a / gamma; gamma = a;
+//               ss = (pb ? b : a)
+//   SCAL_SCALE: a = sum pa;  nrm = a; sc_in = sqrt(target / a); sc_out = 1/sc_in
+enum { SCAL_ALPHA = 0, SCAL_BETA = 1, SCAL_SCALE = 2 };
+struct ScalarArgsHost {
+    int nrhs, nba, nbb;     // partial counts per rhs of pa and pb
+    const double* pa;
+    const double* pb;
+    double* gamma;
+    double* alpha;
+    double* beta;
+    double* ss;
+    int* mask;
+    int* flags;
+    double target;
+    double* sc_in;
+    double* sc_out;
+    double* nrm;
+};
+hipError_t launch_scalars(int kind, const ScalarArgsHost& a, hipStream_t s);
 
 // ---- pack / unpack --------------------------------------------------------
 hipError_t launch_pack_gauge(const Geom& g, int fmt, const void* canon, int canon_f64,
@@ -102,7 +119,7 @@ hipError_t launch_unpack_spinor(const Geom& g, int fmt, int nrhs, const void* pa
 // ---- force ------------------------------------------------------------------
 hipError_t launch_force(const Geom& g, int fmt, const double phase[4][2], const void* u,
                         const void* lam_e, const void* lam_o, const void* r_e,
-                        const void* r_o, double coeff, int project, void* g_canon,
+                        const void* r_o, double coeff, int flags, void* g_canon,
                         int canon_f64, hipStream_t s);
 
 }  // namespace weo

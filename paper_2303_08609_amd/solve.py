@@ -1,0 +1,103 @@
+"""Solver front end over ``wilson_eo_cg`` (torch tensors for buffers).
+
+``cg`` solves M x = b (CGLS) or M^dag M x = b (CG) for 1..16 packed right-hand
+sides, either in one format or as FP64 defect correction around inner solves
+in a low-precision format.  ``bench_solves`` times the solves the benchmark
+reports.
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from . import wilson_eo as W
+from .ops import Format, Lattice, _ptr, _stream
+
+OPS = {"M": W.WEO_OP_M, "MdagM": W.WEO_OP_MDAGM}
+
+
+def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000, x0=None,
+       inner: Format | None = None, u_inner=None, inner_tol=1e-3, max_outer=100,
+       check_every=10, out=None):
+    """Returns (x, info dict).  ``inner`` switches on FP64 defect correction."""
+    p = W.weo_solver_params()
+    p.op = OPS[op]
+    p.nrhs = int(nrhs)
+    p.tol = float(tol)
+    p.maxiter = int(maxiter)
+    p.x0_given = 1 if x0 is not None else 0
+    p.mixed = 1 if inner is not None else 0
+    if inner is not None:
+        p.inner = inner.c
+    p.inner_tol = float(inner_tol)
+    p.max_outer = int(max_outer)
+    p.check_every = int(check_every)
+    nbytes = W.wilson_eo_cg_workspace_bytes(lat.c, fmt.c, p)
+    if nbytes == 0:
+        raise W.WilsonEOError(W.WEO_ERR_ARG, "wilson_eo_cg_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    if out is None:
+        out = lat.new_spinor(fmt, nrhs)
+    if x0 is not None:
+        out.copy_(x0)
+    info = W.weo_solver_info()
+    rc = W.wilson_eo_cg(lat.c, fmt.c, p, _ptr(u), _ptr(u_inner), _ptr(b), _ptr(out), _ptr(ws),
+                        nbytes, info, _stream())
+    W.check(rc, "wilson_eo_cg")
+    res = {"status": info.status, "iters": info.iters, "outer_iters": info.outer_iters,
+           "applies": info.applies, "seconds": info.seconds,
+           "true_rel_resid": [info.true_rel_resid[i] for i in range(nrhs)]}
+    return out, res
+
+
+def bench_solves(lat: Lattice, u_np, psi_np, u_dev64, psi_dev64, reps=1):
+    """Solve M x = b on the benchmark lattice:
+    * plain FP32 CGLS to 1e-6 (its recursive-residual target; true residual
+      reported);
+    * FP64 defect correction to 1e-10 with FP32 inner solves (the plain-FP32
+      path at 1e-10: pure FP32 cannot reach it);
+    * FP64 defect correction to 1e-10 with BF16 spinors / FP16 12-real links
+      and with FP16 spinors / FP16 12-real links inside.
+    Wall times include every kernel of the solve, not the gauge packing."""
+    out = {}
+    f32 = Format("f32", "f32", 18)
+    f64 = Format("f64", "f64", 18)
+    u32 = lat.pack_gauge(u_dev64, f32)
+    b32 = lat.pack_spinor(psi_dev64, f32)
+    u64 = lat.pack_gauge(u_dev64, f64)
+    b64 = lat.pack_spinor(psi_dev64, f64)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, info)
+        return best
+
+    dt, info = timed(lambda: cg(lat, f32, u32, b32, tol=1e-6, maxiter=20000))
+    out["fp32_cgls_1e-6"] = {"seconds": round(dt, 4), "iters": info["iters"],
+                             "true_rel_resid_fp32": info["true_rel_resid"][0],
+                             "status": info["status"]}
+    inners = {"fp32": Format("f32", "f32", 18), "bf16_f16link12": Format("bf16", "f16", 12),
+              "f16_f16link12": Format("f16", "f16", 12)}
+    for name, inner in inners.items():
+        ui = lat.pack_gauge(u_dev64, inner)
+        dt, info = timed(lambda: cg(lat, f64, u64, b64, tol=1e-10, maxiter=50000, inner=inner,
+                                    u_inner=ui, inner_tol=1e-3 if name != "fp32" else 1e-5,
+                                    max_outer=100))
+        out[f"dc_{name}_1e-10"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
+                                   "outer_iters": info["outer_iters"],
+                                   "true_rel_resid_fp64": info["true_rel_resid"][0],
+                                   "status": info["status"]}
+        del ui
+    base = out["dc_fp32_1e-10"]["seconds"]
+    for k in ("dc_bf16_f16link12_1e-10", "dc_f16_f16link12_1e-10"):
+        out[k]["speedup_vs_fp32_inner"] = round(base / out[k]["seconds"], 3)
+    return out

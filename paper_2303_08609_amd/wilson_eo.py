@@ -26,6 +26,7 @@ WEO_F64, WEO_F32, WEO_F16, WEO_BF16 = 0, 1, 2, 3
 WEO_LINK18, WEO_LINK12 = 0, 1
 WEO_MAX_RHS = 16
 WEO_OP_M, WEO_OP_MDAGM = 0, 1
+WEO_FORCE_PROJECT, WEO_FORCE_ACCUMULATE = 1, 2
 
 
 class weo_lattice(C.Structure):
@@ -65,6 +66,12 @@ _SIGS = {
                                 _vp, C.c_int, _vp]),
     "wilson_eo_apply": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, _vp, _vp, _vp,
                                   _vp, C.c_int, _vp]),
+    "wilson_eo_cg_workspace_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format),
+                                                  _P(weo_solver_params)]),
+    "wilson_eo_cg": (C.c_int, [_P(weo_lattice), _P(weo_format), _P(weo_solver_params), _vp, _vp,
+                               _vp, _vp, _vp, C.c_size_t, _P(weo_solver_info), _vp]),
+    "wilson_eo_force": (C.c_int, [_P(weo_lattice), _P(weo_format), _vp, _vp, _vp, _vp, _vp,
+                                  C.c_double, C.c_int, _vp, C.c_int, _vp]),
 }
 
 _lib = None
@@ -122,6 +129,9 @@ weo_pack_spinor = _call("weo_pack_spinor")
 weo_unpack_spinor = _call("weo_unpack_spinor")
 wilson_eo_hop = _call("wilson_eo_hop")
 wilson_eo_apply = _call("wilson_eo_apply")
+wilson_eo_cg_workspace_bytes = _call("wilson_eo_cg_workspace_bytes")
+wilson_eo_cg = _call("wilson_eo_cg")
+wilson_eo_force = _call("wilson_eo_force")
 wilson_eo_strerror = _call("wilson_eo_strerror")
 
 
