@@ -116,6 +116,9 @@ def main():
     ap.add_argument("--variants", default="f32/f32/12,f64/f64/18,f16/f16/12,bf16/f16/12")
     ap.add_argument("--solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-mode", action="store_true",
+                    help="short fixed run for rocprofv3: a 1 GiB device copy (counter "
+                         "calibration) and --steps hop launches per format, nothing else")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
@@ -164,6 +167,25 @@ def main():
         ms_hop = time_loop(hop, max(steps, 1))
         del ud, xd, out, tmp
         return ms_apply, ms_hop
+
+    if a.profile_mode:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        for _ in range(5):
+            dst.copy_(src)
+        del src, dst
+        for vs in [a.format] + [s for s in a.variants.split(",") if s]:
+            f2 = Format(*parse_fmt(vs))
+            ud = lat.pack_gauge(u_dev64, f2)
+            xd = lat.pack_spinor(psi_dev64, f2)
+            tmp = lat.new_spinor(f2)
+            for _ in range(a.steps):
+                lat.hop(ud, xd, f2, out_parity=1, out=tmp)
+            torch.cuda.synchronize()
+            print(f"[bench] profiled {a.steps} hop launches of {vs}", file=sys.stderr, flush=True)
+            del ud, xd, tmp
+        return
 
     fs = parse_fmt(a.format)
     ms_apply, ms_hop = run_format(fs, a.steps, a.warmup)

@@ -48,19 +48,23 @@ def sources():
     return hip, cpp
 
 
-def build(jobs: int | None = None, debug: bool = False, verbose: bool = False) -> str:
+def build(jobs: int | None = None, debug: bool = False, verbose: bool = False,
+          defines=(), out: str | None = None) -> str:
+    """Compile and link; ``defines`` are extra -D options for the HIP sources
+    (launch-shape knobs), ``out`` an alternative library path."""
     os.makedirs(BUILD, exist_ok=True)
     hip, cpp = sources()
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     cmds = []
     objs = []
+    tag = ("_" + "_".join(defines)) if defines else ""
     for f in hip:
-        o = os.path.join(BUILD, f + ".o")
+        o = os.path.join(BUILD, f + tag + ".o")
         objs.append(o)
         cmds.append([hipcc] + HIPCC_FLAGS + (["-g"] if debug else []) +
-                    ["-c", os.path.join(CSRC, f), "-o", o])
+                    [f"-D{d}" for d in defines] + ["-c", os.path.join(CSRC, f), "-o", o])
     for f in cpp:
-        o = os.path.join(BUILD, f + ".o")
+        o = os.path.join(BUILD, f + tag + ".o")
         objs.append(o)
         cmds.append(["g++"] + CXX_FLAGS + (["-g"] if debug else []) +
                     ["-c", os.path.join(CSRC, f), "-o", o])
@@ -69,11 +73,12 @@ def build(jobs: int | None = None, debug: bool = False, verbose: bool = False) -
         for err in ex.map(_run, cmds):
             if verbose and err.strip():
                 print(err, file=sys.stderr)
-    tmp = LIB + ".tmp"
+    lib = out or LIB
+    tmp = lib + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs +
          [f"-L{ROCM}/lib", "-lamdhip64"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def main(argv=None):
@@ -81,8 +86,11 @@ def main(argv=None):
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--debug", action="store_true")
     ap.add_argument("-v", "--verbose", action="store_true")
+    ap.add_argument("-D", dest="defines", action="append", default=[],
+                    help="extra preprocessor definition for the HIP sources, e.g. -D WEO_NT_LINKS=1")
+    ap.add_argument("--out", default=None, help="library path (default: in the package)")
     a = ap.parse_args(argv)
-    print(build(a.jobs, a.debug, a.verbose))
+    print(build(a.jobs, a.debug, a.verbose, tuple(a.defines), a.out))
 
 
 if __name__ == "__main__":

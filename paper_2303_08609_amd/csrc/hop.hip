@@ -26,6 +26,41 @@
 
 namespace weo {
 
+// Per-precision kernel shape, chosen by measurement on MI355X at 32^3x64:
+//   pipe  d >= 1: the raw words of neighbour k + d are loaded while neighbour
+//         k is computed (a register ring of d + 1 records, kept in order by
+//         scheduling barriers); 0: one direction at a time as written.
+//   nt    links are read with streaming (non-temporal) loads: every link is
+//         used once per hop, so it should not evict the spinors that the
+//         neighbouring sites re-read through L2.
+// FP64 keeps regular link loads (its streaming variant measured slower) and
+// a one-deep ring (a two-deep ring spills); FP16/BF16 records are small
+// enough for a two-deep ring.  WEO_HOP_PIPE / WEO_NT_LINKS (-D) override all
+// precisions at once for experiments.
+template <int SP> struct HopShape;
+template <> struct HopShape<P_F64> { static constexpr int pipe = 1; static constexpr bool nt = false; };
+template <> struct HopShape<P_F32> { static constexpr int pipe = 1; static constexpr bool nt = true; };
+template <> struct HopShape<P_F16> { static constexpr int pipe = 2; static constexpr bool nt = true; };
+template <> struct HopShape<P_BF16> { static constexpr int pipe = 2; static constexpr bool nt = true; };
+#ifdef WEO_HOP_PIPE
+template <int SP> constexpr int hop_pipe() { return WEO_HOP_PIPE; }
+#else
+template <int SP> constexpr int hop_pipe() { return HopShape<SP>::pipe; }
+#endif
+#ifdef WEO_NT_LINKS
+template <int SP> constexpr bool hop_nt() { return WEO_NT_LINKS != 0; }
+#else
+template <int SP> constexpr bool hop_nt() { return HopShape<SP>::nt; }
+#endif
+//   WEO_WAVES_F32 / WEO_WAVES_F64: minimum waves per SIMD requested (0 = the
+//   compiler's choice).
+#ifndef WEO_WAVES_F32
+#define WEO_WAVES_F32 0
+#endif
+#ifndef WEO_WAVES_F64
+#define WEO_WAVES_F64 0
+#endif
+
 template <int SP> struct Arith { using R = float; };
 template <> struct Arith<P_F64> { using R = double; };
 
@@ -46,35 +81,36 @@ struct HopParams {
 
 // Link U as 9 complex numbers (row-major); a 12-real record is completed with
 // row 2 = conj(row0 x row1), exact for det U = 1.
-template <int LP, bool L12, class C>
+template <int LP, bool L12, bool NT = false, class C>
 __device__ __forceinline__ void load_link(const uint8_t* base, uint32_t n, uint32_t i, C* u) {
     if constexpr (L12) {
-        load_rec<LP, 6>(base, n, i, u);
+        load_rec<LP, 6, NT>(base, n, i, u);
         u[6] = conj_(sub(mul(u[1], u[5]), mul(u[2], u[4])));
         u[7] = conj_(sub(mul(u[2], u[3]), mul(u[0], u[5])));
         u[8] = conj_(sub(mul(u[0], u[4]), mul(u[1], u[3])));
     } else {
-        load_rec<LP, 9>(base, n, i, u);
+        load_rec<LP, 9, NT>(base, n, i, u);
     }
 }
 
 // Link record of a precision possibly narrower than the arithmetic type.
-template <int LP, bool L12, class C>
+template <int LP, bool L12, bool NT, class C>
 __device__ __forceinline__ void load_link_as(const uint8_t* base, uint32_t n, uint32_t i, C* u) {
     using LR = typename St<LP>::real;
     if constexpr (sizeof(LR) == sizeof(decltype(C().x))) {
-        load_link<LP, L12>(base, n, i, u);
+        load_link<LP, L12, NT>(base, n, i, u);
     } else {
         cx<LR> w[9];
-        load_link<LP, L12>(base, n, i, w);
+        load_link<LP, L12, NT>(base, n, i, w);
 #pragma unroll
         for (int k = 0; k < 9; ++k) { u[k].x = w[k].x; u[k].y = w[k].y; }
     }
 }
 
-// One direction: project with (1 - S gamma_mu), optional boundary phase,
-// multiply by U (FWD) or U^dag (!FWD), reconstruct and accumulate.
-template <int MU, int S, bool FWD, class C>
+// One direction: project with (1 - S gamma_mu), boundary phase (complex when
+// CPH, else real), multiply by U (FWD) or U^dag (!FWD), reconstruct and
+// accumulate.
+template <int MU, int S, bool FWD, bool CPH, class C>
 __device__ __forceinline__ void hop_dir(const C* p, const C* u, bool edge, C phase, C* acc) {
     C h0[3], h1[3];
 #pragma unroll
@@ -94,9 +130,16 @@ __device__ __forceinline__ void hop_dir(const C* p, const C* u, bool edge, C pha
             h1[c] = S > 0 ? p3 : p1;
         }
     }
-    if (edge) {
+    // Boundary phase: applied without a branch, so that the loads of the
+    // next neighbours can be scheduled ahead of this arithmetic.
+    if constexpr (CPH) {
+        const C ph = edge ? phase : mk<C>(1, 0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) { h0[c] = mul(phase, h0[c]); h1[c] = mul(phase, h1[c]); }
+        for (int c = 0; c < 3; ++c) { h0[c] = mul(ph, h0[c]); h1[c] = mul(ph, h1[c]); }
+    } else {
+        const auto sg = edge ? phase.x : decltype(phase.x)(1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { h0[c] = scal(sg, h0[c]); h1[c] = scal(sg, h1[c]); }
     }
     C g0[3], g1[3];
 #pragma unroll
@@ -146,7 +189,7 @@ __device__ __forceinline__ void hop_dir(const C* p, const C* u, bool edge, C pha
 }
 
 // Both neighbours of direction MU for one rhs.
-template <int SP, int LP, bool L12, bool DAG, int MU, class C>
+template <int SP, int LP, bool L12, bool DAG, bool CPH, int MU, class C>
 __device__ __forceinline__ void hop_mu(const HopParams& P, const uint8_t* in, const Nbr& nb,
                                        uint32_t ih, C* acc) {
     constexpr int SF = DAG ? -1 : 1;      // forward term: (1 - SF gamma)
@@ -156,16 +199,83 @@ __device__ __forceinline__ void hop_mu(const HopParams& P, const uint8_t* in, co
     phase.y = (decltype(C().x))P.ph[MU][1];
     {
         C u[9], p[12];
-        load_link_as<LP, L12>(P.u + (size_t)(2 * MU + P.out_par) * P.link_block, n, ih, u);
+        load_link_as<LP, L12, hop_nt<SP>()>(P.u + (size_t)(2 * MU + P.out_par) * P.link_block, n, ih, u);
         load_rec<SP, 12>(in, n, nb.i[2 * MU], p);
-        hop_dir<MU, SF, true>(p, u, nb.edge[2 * MU], phase, acc);
+        hop_dir<MU, SF, true, CPH>(p, u, nb.edge[2 * MU], phase, acc);
     }
     {
         C u[9], p[12];
         const uint32_t j = nb.i[2 * MU + 1];
-        load_link_as<LP, L12>(P.u + (size_t)(2 * MU + 1 - P.out_par) * P.link_block, n, j, u);
+        load_link_as<LP, L12, hop_nt<SP>()>(P.u + (size_t)(2 * MU + 1 - P.out_par) * P.link_block, n, j, u);
         load_rec<SP, 12>(in, n, j, p);
-        hop_dir<MU, -SF, false>(p, u, nb.edge[2 * MU + 1], conj_(phase), acc);
+        hop_dir<MU, -SF, false, CPH>(p, u, nb.edge[2 * MU + 1], conj_(phase), acc);
+    }
+}
+
+// ---- pipelined form ---------------------------------------------------------
+// Neighbour k = 2 mu + (0: forward x + mu, 1: backward x - mu).
+template <int SP, int LP, bool L12>
+struct NbrRaw {
+    RawRec<SP, 12> sp;
+    RawRec<LP, L12 ? 6 : 9, hop_nt<SP>()> ln;
+};
+
+template <int SP, int LP, bool L12, int K>
+__device__ __forceinline__ void issue(const HopParams& P, const uint8_t* in, const Nbr& nb, uint32_t ih,
+                                      NbrRaw<SP, LP, L12>& r) {
+    constexpr int MU = K / 2;
+    const uint32_t n = P.g.vh;
+    if constexpr ((K & 1) == 0) {
+        r.ln.load(P.u + (size_t)(2 * MU + P.out_par) * P.link_block, n, ih);
+    } else {
+        r.ln.load(P.u + (size_t)(2 * MU + 1 - P.out_par) * P.link_block, n, nb.i[K]);
+    }
+    r.sp.load(in, n, nb.i[K]);
+}
+
+template <int SP, int LP, bool L12, bool DAG, bool CPH, int K, class C>
+__device__ __forceinline__ void consume(const HopParams& P, const Nbr& nb, const NbrRaw<SP, LP, L12>& r,
+                                        C* acc) {
+    constexpr int MU = K / 2;
+    constexpr int SF = DAG ? -1 : 1;
+    using R = decltype(C().x);
+    C p[12], u[9];
+    r.sp.unpack(p);
+    {
+        using LR = typename St<LP>::real;
+        cx<LR> w[9];
+        r.ln.unpack(w);
+#pragma unroll
+        for (int k = 0; k < (L12 ? 6 : 9); ++k) { u[k].x = (R)w[k].x; u[k].y = (R)w[k].y; }
+        if constexpr (L12) {
+            u[6] = conj_(sub(mul(u[1], u[5]), mul(u[2], u[4])));
+            u[7] = conj_(sub(mul(u[2], u[3]), mul(u[0], u[5])));
+            u[8] = conj_(sub(mul(u[0], u[4]), mul(u[1], u[3])));
+        }
+    }
+    C phase;
+    phase.x = (R)P.ph[MU][0];
+    phase.y = (R)P.ph[MU][1];
+    if constexpr ((K & 1) == 0) hop_dir<MU, SF, true, CPH>(p, u, nb.edge[K], phase, acc);
+    else hop_dir<MU, -SF, false, CPH>(p, u, nb.edge[K], conj_(phase), acc);
+}
+
+template <int SP, int LP, bool L12, bool DAG, bool CPH, int D, int K, class C>
+__device__ __forceinline__ void pipe_step(const HopParams& P, const uint8_t* in, const Nbr& nb, uint32_t ih,
+                                          NbrRaw<SP, LP, L12> (&ring)[D + 1], C* acc) {
+    if constexpr (K + D < 8) issue<SP, LP, L12, K + D>(P, in, nb, ih, ring[(K + D) % (D + 1)]);
+    __builtin_amdgcn_sched_barrier(0);
+    consume<SP, LP, L12, DAG, CPH, K>(P, nb, ring[K % (D + 1)], acc);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (K + 1 < 8) pipe_step<SP, LP, L12, DAG, CPH, D, K + 1>(P, in, nb, ih, ring, acc);
+}
+
+template <int SP, int LP, bool L12, bool DAG, bool CPH, int D, int K = 0>
+__device__ __forceinline__ void pipe_prologue(const HopParams& P, const uint8_t* in, const Nbr& nb, uint32_t ih,
+                                              NbrRaw<SP, LP, L12> (&ring)[D + 1]) {
+    if constexpr (K < D) {
+        issue<SP, LP, L12, K>(P, in, nb, ih, ring[K]);
+        pipe_prologue<SP, LP, L12, DAG, CPH, D, K + 1>(P, in, nb, ih, ring);
     }
 }
 
@@ -184,8 +294,11 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     return s;
 }
 
-template <int SP, int LP, bool L12, bool DAG, bool AXPY, bool NORM>
-__global__ void __launch_bounds__(256) k_hop(const HopParams P) {
+template <int SP> struct Waves { static constexpr int n = WEO_WAVES_F32; };
+template <> struct Waves<P_F64> { static constexpr int n = WEO_WAVES_F64; };
+
+template <int SP, int LP, bool L12, bool DAG, bool AXPY, bool NORM, bool CPH>
+__global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_hop(const HopParams P) {
     using R = typename Arith<SP>::R;
     using C = cx<R>;
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x, P.remap);
@@ -200,10 +313,17 @@ __global__ void __launch_bounds__(256) k_hop(const HopParams P) {
         C acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = czero<C>();
-        hop_mu<SP, LP, L12, DAG, 0>(P, in, nb, ih, acc);
-        hop_mu<SP, LP, L12, DAG, 1>(P, in, nb, ih, acc);
-        hop_mu<SP, LP, L12, DAG, 2>(P, in, nb, ih, acc);
-        hop_mu<SP, LP, L12, DAG, 3>(P, in, nb, ih, acc);
+        constexpr int D = hop_pipe<SP>();
+        if constexpr (D > 0) {
+            NbrRaw<SP, LP, L12> ring[D + 1];
+            pipe_prologue<SP, LP, L12, DAG, CPH, D>(P, in, nb, ih, ring);
+            pipe_step<SP, LP, L12, DAG, CPH, D, 0>(P, in, nb, ih, ring, acc);
+        } else {
+            hop_mu<SP, LP, L12, DAG, CPH, 0>(P, in, nb, ih, acc);
+            hop_mu<SP, LP, L12, DAG, CPH, 1>(P, in, nb, ih, acc);
+            hop_mu<SP, LP, L12, DAG, CPH, 2>(P, in, nb, ih, acc);
+            hop_mu<SP, LP, L12, DAG, CPH, 3>(P, in, nb, ih, acc);
+        }
         if constexpr (AXPY) {
             C yv[12];
             load_rec<SP, 12>(P.y + (size_t)rhs * P.spinor_bytes, P.g.vh, ih, yv);
@@ -261,10 +381,15 @@ template <int SP, int LP, bool L12>
 static hipError_t launch_fmt(const HopLaunch& h, const HopParams& P, dim3 grid, dim3 block,
                              hipStream_t s) {
     const bool axpy = h.y != nullptr, norm = h.partial != nullptr;
-#define WEO_HOP_CASE(D, A, N)                                                         \
-    if (h.dagger == D && axpy == A && norm == N) {                                    \
-        hipLaunchKernelGGL((k_hop<SP, LP, L12, D, A, N>), grid, block, 0, s, P);      \
-        return hipGetLastError();                                                     \
+    bool cph = false;
+    for (int m = 0; m < 4; ++m) cph = cph || h.phase[m][1] != 0.0;
+#define WEO_HOP_CASE(D, A, N)                                                            \
+    if (h.dagger == D && axpy == A && norm == N) {                                       \
+        if (cph)                                                                          \
+            hipLaunchKernelGGL((k_hop<SP, LP, L12, D, A, N, true>), grid, block, 0, s, P);  \
+        else                                                                              \
+            hipLaunchKernelGGL((k_hop<SP, LP, L12, D, A, N, false>), grid, block, 0, s, P); \
+        return hipGetLastError();                                                         \
     }
     WEO_HOP_CASE(0, false, false) WEO_HOP_CASE(1, false, false)
     WEO_HOP_CASE(0, true, false)  WEO_HOP_CASE(1, true, false)

@@ -137,10 +137,10 @@ template <> struct St<P_F16> {
 // bfloat16: the upper 16 bits of an IEEE binary32; conversion rounds to
 // nearest even, NaN stays NaN.
 __device__ __forceinline__ uint32_t f_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t qnan = (u >> 16) | 0x40u;
+    return ((u & 0x7fffffffu) > 0x7f800000u) ? qnan : rne;   // a select, no branch
 }
 __device__ __forceinline__ float2 bf2_to_f2(uint32_t w) {
     return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
@@ -182,23 +182,71 @@ template <int P, int NC> struct Rec {
     static constexpr int BYTES = NC * CB;
 };
 
-template <int P, int NC, class V>
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+// Plain or streaming (non-temporal: the line is not kept in the caches for
+// reuse) loads of 16, 8 and 4 bytes.
+template <bool NT> __device__ __forceinline__ uint4 ld16(const uint8_t* p) {
+    if constexpr (NT) {
+        const u32x4_t w = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+        return make_uint4(w.x, w.y, w.z, w.w);
+    } else {
+        return *reinterpret_cast<const uint4*>(p);
+    }
+}
+template <bool NT> __device__ __forceinline__ uint2 ld8(const uint8_t* p) {
+    if constexpr (NT) {
+        const u32x2_t w = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t*>(p));
+        return make_uint2(w.x, w.y);
+    } else {
+        return *reinterpret_cast<const uint2*>(p);
+    }
+}
+template <bool NT> __device__ __forceinline__ uint32_t ld4(const uint8_t* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+    else return *reinterpret_cast<const uint32_t*>(p);
+}
+
+template <int P, int NC, bool NT = false, class V>
 __device__ __forceinline__ void load_rec(const uint8_t* __restrict__ base, uint32_t n, uint32_t i, V* v) {
     using T = Rec<P, NC>;
     const size_t pb = (size_t)n * 16;
 #pragma unroll
     for (int p = 0; p < T::NFULL; ++p) {
-        const uint4 w = *reinterpret_cast<const uint4*>(base + p * pb + (uint32_t)(i * 16u));
+        const uint4 w = ld16<NT>(base + p * pb + (uint32_t)(i * 16u));
         St<P>::unpack16(w, v + p * T::K);
     }
     if constexpr (T::TAILB == 8) {
-        const uint2 w = *reinterpret_cast<const uint2*>(base + T::NFULL * pb + (uint32_t)(i * 8u));
+        const uint2 w = ld8<NT>(base + T::NFULL * pb + (uint32_t)(i * 8u));
         St<P>::unpack8(w, v + T::NFULL * T::K);
     } else if constexpr (T::TAILB == 4) {
-        const uint32_t w = *reinterpret_cast<const uint32_t*>(base + T::NFULL * pb + (uint32_t)(i * 4u));
+        const uint32_t w = ld4<NT>(base + T::NFULL * pb + (uint32_t)(i * 4u));
         St<P>::unpack4(w, v + T::NFULL * T::K);
     }
 }
+
+// A record held as the raw words of its planes, so that loads can be issued
+// well before the values are needed without keeping unpacked copies live.
+template <int P, int NC, bool NT = false> struct RawRec {
+    using T = Rec<P, NC>;
+    uint4 w[T::NFULL > 0 ? T::NFULL : 1];
+    uint2 t8;
+    uint32_t t4;
+    __device__ __forceinline__ void load(const uint8_t* __restrict__ base, uint32_t n, uint32_t i) {
+        const size_t pb = (size_t)n * 16;
+#pragma unroll
+        for (int p = 0; p < T::NFULL; ++p) w[p] = ld16<NT>(base + p * pb + (uint32_t)(i * 16u));
+        if constexpr (T::TAILB == 8) t8 = ld8<NT>(base + T::NFULL * pb + (uint32_t)(i * 8u));
+        if constexpr (T::TAILB == 4) t4 = ld4<NT>(base + T::NFULL * pb + (uint32_t)(i * 4u));
+    }
+    template <class V> __device__ __forceinline__ void unpack(V* v) const {
+#pragma unroll
+        for (int p = 0; p < T::NFULL; ++p) St<P>::unpack16(w[p], v + p * T::K);
+        if constexpr (T::TAILB == 8) St<P>::unpack8(t8, v + T::NFULL * T::K);
+        if constexpr (T::TAILB == 4) St<P>::unpack4(t4, v + T::NFULL * T::K);
+    }
+};
 
 template <int P, int NC, class V>
 __device__ __forceinline__ void store_rec(uint8_t* __restrict__ base, uint32_t n, uint32_t i, const V* v) {
