@@ -103,6 +103,24 @@ int weo_selftest(void);
 /* 1 if the format combination is built into this library, else 0. */
 int weo_format_supported(const weo_format* fmt);
 
+/* Launch shape of hops with nrhs > 1 (used by hop, apply and the solvers).
+ * The multi-rhs kernel loads each link once per lane and applies it to nr
+ * right-hand sides (the batching the paper's solvers would need for many
+ * sources; the paper itself treats one).  nr = 0 (default): an autotuner
+ * times every candidate shape on the first call per (lattice, format,
+ * nrhs) -- on the caller's stream and buffers, with one stream
+ * synchronisation -- and caches the fastest for the process.  nr = 1: one
+ * lane per (site, rhs).  nr in {2, 3, 4, 6} (FP64 uses at most 3) with
+ * sites per workgroup in {64, 128, 256} and persist in {0, 1} forces that
+ * shape.  Returns WEO_ERR_ARG for other values.  Not thread-safe with
+ * respect to concurrent hops on other threads changing the setting. */
+int weo_set_mrhs_shape(int nr, int sites, int persist);
+
+/* The autotuner's cached choices as JSON lines in buf (NUL-terminated,
+ * truncated to len bytes); returns the untruncated length.  buf may be NULL
+ * to query the length. */
+int weo_tuning_report(char* buf, size_t len);
+
 /* Bytes of the packed gauge field (all 4V links) in format fmt; 0 on error. */
 size_t weo_gauge_bytes(const weo_lattice* lat, const weo_format* fmt);
 

@@ -113,6 +113,17 @@ const char* wilson_eo_strerror(int code) {
 
 int weo_format_supported(const weo_format* fmt) { return format_id(fmt) >= 0 ? 1 : 0; }
 
+int weo_set_mrhs_shape(int nr, int sites, int persist) {
+    return set_mrhs_shape(nr, sites, persist) == 0 ? WEO_OK : WEO_ERR_ARG;
+}
+
+int weo_tuning_report(char* buf, size_t len) {
+    if (buf && len) buf[0] = 0;
+    const int n = tuning_report(buf, len);
+    if (buf && len) buf[len - 1] = 0;
+    return n;
+}
+
 size_t weo_gauge_bytes(const weo_lattice* lat, const weo_format* fmt) {
     Geom g;
     int id;

@@ -1,0 +1,410 @@
+// Multi right-hand-side hopping kernel and its autotuner.
+//
+// A lane owns one output site and a group of NR right-hand sides: each link
+// is loaded once and applied to NR spinors, so for 12 right-hand sides the
+// link traffic falls by NR compared with 12 single-rhs launches; the NR
+// spinor loads per neighbour also give each lane more independent memory
+// requests in flight.  The boundary phase is folded into the link once per
+// neighbour ((ph U) h forward, (ph U)^dag h = conj(ph) U^dag h backward)
+// instead of into NR half spinors.
+//
+// Workgroups are blockDim.x sites (a multiple of 64) by blockDim.y groups of
+// NR rhs (at most 256 lanes), further groups in grid rows; each wavefront
+// therefore has one rhs group, and the groups of one workgroup share their
+// links through the caches.  Optionally the grid is
+// persistent (a multiple of 8 workgroups looping over site blocks), with the
+// same XCD-contiguous block order as the single-rhs kernel.
+//
+// The launch shape (NR, sites per workgroup, persistence) is picked per
+// (lattice, format, nrhs) by timing every candidate on the first call with
+// that key on the caller's stream and buffers (one stream synchronisation),
+// then cached for the life of the process.  WEO_TUNE=0 in the environment
+// disables the search and uses NR = 3, 64 sites, no persistence.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "hop_core.h"
+
+namespace weo {
+
+struct MrhsParams {
+    HopParams h;
+    int nrhs;
+    uint32_t nblk;      // site blocks of blockDim.x sites
+};
+
+// Raw words of one neighbour: its link and the NR spinor records.
+template <int SP, int LP, bool L12, int NR>
+struct MrhsRaw {
+    RawRec<LP, L12 ? 6 : 9, hop_nt<SP>()> ln;
+    RawRec<SP, 12> sp[NR];
+};
+
+template <int SP, int LP, bool L12, int NR, int K>
+__device__ __forceinline__ void mrhs_issue(const MrhsParams& M, const Nbr& nb, uint32_t ih, int r0,
+                                           MrhsRaw<SP, LP, L12, NR>& r) {
+    constexpr int MU = K / 2;
+    constexpr bool FWD = (K & 1) == 0;
+    const HopParams& P = M.h;
+    const uint32_t n = P.g.vh;
+    r.ln.load(P.u + (size_t)(2 * MU + (FWD ? P.out_par : 1 - P.out_par)) * P.link_block, n,
+              FWD ? ih : nb.i[K]);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        // rhs beyond nrhs (last group) recompute the last one; never stored
+        const int rr = r0 + q < M.nrhs ? r0 + q : M.nrhs - 1;
+        r.sp[q].load(P.in + (size_t)rr * P.spinor_bytes, n, nb.i[K]);
+    }
+}
+
+template <int SP, int LP, bool L12, bool DAG, int NR, int K, class C>
+__device__ __forceinline__ void mrhs_consume(const MrhsParams& M, const Nbr& nb,
+                                             const MrhsRaw<SP, LP, L12, NR>& r, C (&acc)[NR][12]) {
+    constexpr int MU = K / 2;
+    constexpr bool FWD = (K & 1) == 0;
+    constexpr int SF = DAG ? -1 : 1;
+    using R = decltype(C().x);
+    const HopParams& P = M.h;
+    C u[9];
+    {
+        cx<typename St<LP>::real> w[9];
+        r.ln.unpack(w);
+#pragma unroll
+        for (int k = 0; k < (L12 ? 6 : 9); ++k) { u[k].x = (R)w[k].x; u[k].y = (R)w[k].y; }
+        if constexpr (L12) {
+            u[6] = conj_(sub(mul(u[1], u[5]), mul(u[2], u[4])));
+            u[7] = conj_(sub(mul(u[2], u[3]), mul(u[0], u[5])));
+            u[8] = conj_(sub(mul(u[0], u[4]), mul(u[1], u[3])));
+        }
+        const C ph = nb.edge[K] ? mk<C>((R)P.ph[MU][0], (R)P.ph[MU][1]) : mk<C>(R(1), R(0));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) u[k] = mul(ph, u[k]);
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        C p[12];
+        r.sp[q].unpack(p);
+        hop_dir<MU, FWD ? SF : -SF, FWD, false, C, false>(p, u, false, C{}, acc[q]);
+    }
+}
+
+// Prefetch depth: with D = 1 the next neighbour's words are loaded while this
+// one is computed; for larger NR the doubled raw storage costs more
+// occupancy than the overlap gains, so D = 0 (the NR + 1 records of one
+// neighbour are still in flight together).
+template <int SP, int NR> constexpr int mrhs_depth() {
+    if constexpr (SP == P_F64) return 0;
+    else if constexpr (SP == P_F32) return NR <= 2 ? 1 : 0;
+    else return NR <= 3 ? 1 : 0;
+}
+
+template <int SP, int LP, bool L12, bool DAG, int NR, int D, int K, class C>
+__device__ __forceinline__ void mrhs_step(const MrhsParams& M, const Nbr& nb, uint32_t ih, int r0,
+                                          MrhsRaw<SP, LP, L12, NR> (&ring)[D + 1], C (&acc)[NR][12]) {
+    if constexpr (D == 0) mrhs_issue<SP, LP, L12, NR, K>(M, nb, ih, r0, ring[0]);
+    else if constexpr (K + 1 < 8) mrhs_issue<SP, LP, L12, NR, K + 1>(M, nb, ih, r0, ring[(K + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    mrhs_consume<SP, LP, L12, DAG, NR, K>(M, nb, ring[D == 0 ? 0 : (K & 1)], acc);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (K + 1 < 8) mrhs_step<SP, LP, L12, DAG, NR, D, K + 1>(M, nb, ih, r0, ring, acc);
+}
+
+template <int SP, int LP, bool L12, bool DAG, int NR>
+__global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
+    using R = typename Arith<SP>::R;
+    using C = cx<R>;
+    const HopParams& P = M.h;
+    // the rhs group is uniform across a wavefront (blockDim.x is a multiple
+    // of 64): keep it in a scalar register so that every spinor address is a
+    // scalar base plus the lane's 32-bit offset
+    const int r0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * blockDim.y + threadIdx.y) * NR);
+    const uint32_t S = blockDim.x;
+    const uint32_t nchunk = (P.g.vh + 63) >> 6;
+    for (uint32_t b = blockIdx.x; b < M.nblk; b += gridDim.x) {
+        const uint32_t blk = xcd_block(b, M.nblk, P.remap);
+        const uint32_t ih = blk * S + threadIdx.x;
+        double nrm[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) nrm[q] = 0.0;
+        if (ih < P.g.vh && r0 < M.nrhs) {
+            const Site s = decode(P.g, ih, P.out_par);
+            const Nbr nb = neighbours(P.g, s);
+            C acc[NR][12];
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[q][k] = czero<C>();
+            constexpr int D = mrhs_depth<SP, NR>();
+            MrhsRaw<SP, LP, L12, NR> ring[D + 1];
+            if constexpr (D > 0) mrhs_issue<SP, LP, L12, NR, 0>(M, nb, ih, r0, ring[0]);
+            mrhs_step<SP, LP, L12, DAG, NR, D, 0>(M, nb, ih, r0, ring, acc);
+            // Pin the accumulators here: the epilogue below is conditional per
+            // rhs, and without this the compiler sinks the whole accumulation
+            // of the later rhs into those branches, keeping every partial
+            // product live until the end.
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+#pragma unroll
+                for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(acc[q][k].x), "+v"(acc[q][k].y));
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const int r = r0 + q;
+                if (r < M.nrhs) {
+                    if (P.y) {
+                        C yv[12];
+                        load_rec<SP, 12>(P.y + (size_t)r * P.spinor_bytes, P.g.vh, ih, yv);
+                        const R a = (R)P.alpha;
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) {
+                            acc[q][k].x = fma(a, acc[q][k].x, yv[k].x);
+                            acc[q][k].y = fma(a, acc[q][k].y, yv[k].y);
+                        }
+                    }
+                    uint8_t* out = P.out + (size_t)r * P.spinor_bytes;
+                    store_rec<SP, 12>(out, P.g.vh, ih, acc[q]);
+                    if (P.partial) {
+                        C st[12];
+                        if constexpr (SP == P_F64 || SP == P_F32) {
+#pragma unroll
+                            for (int k = 0; k < 12; ++k) st[k] = acc[q][k];
+                        } else {
+                            load_rec<SP, 12>(out, P.g.vh, ih, st);
+                        }
+#pragma unroll
+                        for (int k = 0; k < 12; ++k)
+                            nrm[q] += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
+                    }
+                }
+            }
+        }
+        if (P.partial) {
+            const uint32_t chunk = (blk * S + (threadIdx.x & ~63u)) >> 6;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const double t = wave_sum64(nrm[q]);
+                if ((threadIdx.x & 63) == 0 && chunk < nchunk && r0 + q < M.nrhs)
+                    P.partial[(size_t)(r0 + q) * nchunk + chunk] = t;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host ----
+static HopParams hop_params(const HopLaunch& h) {
+    HopParams P;
+    P.g = h.g;
+    P.out_par = h.out_par;
+    P.remap = hop_tune().remap;
+    for (int m = 0; m < 4; ++m) { P.ph[m][0] = h.phase[m][0]; P.ph[m][1] = h.phase[m][1]; }
+    P.u = static_cast<const uint8_t*>(h.u);
+    P.in = static_cast<const uint8_t*>(h.in);
+    P.out = static_cast<uint8_t*>(h.out);
+    P.y = static_cast<const uint8_t*>(h.y);
+    P.alpha = h.alpha;
+    P.partial = h.partial;
+    P.spinor_bytes = spinor_field_bytes(h.g, h.fmt);
+    P.link_block = gauge_block_bytes(h.g, h.fmt);
+    return P;
+}
+
+template <int SP, int LP, bool L12, int NR>
+static hipError_t mrhs_nr(const HopLaunch& h, const MrhsParams& M, dim3 grid, dim3 block, hipStream_t s) {
+    if (h.dagger)
+        hipLaunchKernelGGL((k_hop_mrhs<SP, LP, L12, true, NR>), grid, block, 0, s, M);
+    else
+        hipLaunchKernelGGL((k_hop_mrhs<SP, LP, L12, false, NR>), grid, block, 0, s, M);
+    return hipGetLastError();
+}
+
+template <int SP, int LP, bool L12>
+static hipError_t mrhs_fmt(const HopLaunch& h, const MrhsParams& M, int nr, dim3 grid, dim3 block,
+                           hipStream_t s) {
+    switch (nr) {
+        case 2: return mrhs_nr<SP, LP, L12, 2>(h, M, grid, block, s);
+        case 3: return mrhs_nr<SP, LP, L12, 3>(h, M, grid, block, s);
+        default: break;
+    }
+    if constexpr (SP != P_F64) {
+        switch (nr) {
+            case 4: return mrhs_nr<SP, LP, L12, 4>(h, M, grid, block, s);
+            case 6: return mrhs_nr<SP, LP, L12, 6>(h, M, grid, block, s);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) {
+    MrhsParams M;
+    M.h = hop_params(h);
+    M.nrhs = h.nrhs;
+    M.nblk = (h.g.vh + (uint32_t)c.s - 1) / (uint32_t)c.s;
+    const int groups = (h.nrhs + c.nr - 1) / c.nr;
+    int gy = 256 / c.s;
+    if (gy > groups) gy = groups;
+    const dim3 block((unsigned)c.s, (unsigned)gy);
+    uint32_t nwg = M.nblk;
+    if (c.persist) {
+        const uint32_t cap = 8u * 256u;
+        if (nwg > cap) nwg = cap;
+        nwg = ((nwg + 7u) / 8u) * 8u;
+    }
+    const dim3 grid(nwg, (unsigned)((groups + gy - 1) / gy));
+    switch (h.fmt) {
+        case FMT_D_D_18: return mrhs_fmt<P_F64, P_F64, false>(h, M, c.nr, grid, block, s);
+        case FMT_D_D_12: return mrhs_fmt<P_F64, P_F64, true>(h, M, c.nr, grid, block, s);
+        case FMT_S_S_18: return mrhs_fmt<P_F32, P_F32, false>(h, M, c.nr, grid, block, s);
+        case FMT_S_S_12: return mrhs_fmt<P_F32, P_F32, true>(h, M, c.nr, grid, block, s);
+        case FMT_H_H_18: return mrhs_fmt<P_F16, P_F16, false>(h, M, c.nr, grid, block, s);
+        case FMT_H_H_12: return mrhs_fmt<P_F16, P_F16, true>(h, M, c.nr, grid, block, s);
+        case FMT_B_H_18: return mrhs_fmt<P_BF16, P_F16, false>(h, M, c.nr, grid, block, s);
+        case FMT_B_H_12: return mrhs_fmt<P_BF16, P_F16, true>(h, M, c.nr, grid, block, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+
+using TuneKey = std::tuple<int, int, int, int, int, int>;   // dims, format, nrhs
+
+struct TuneEntry {
+    MrhsCfg cfg;       // nr == 1: the single-rhs kernel
+    float us;
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+
+std::vector<MrhsCfg> candidates(const HopLaunch& h) {
+    std::vector<MrhsCfg> v;
+    v.push_back({1, 0, 0});
+    const bool wide = fmt_info(h.fmt).spinor_prec == P_F64;
+    const int nrs[] = {2, 3, 4, 6};
+    for (int nr : nrs) {
+        if (nr > h.nrhs || (wide && nr > 3)) continue;
+        for (int s : {64, 128, 256})
+            for (int persist : {0, 1}) v.push_back({nr, s, persist});
+    }
+    return v;
+}
+
+hipError_t run_cfg(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) {
+    return c.nr == 1 ? launch_hop_single(h, s) : launch_hop_mrhs(h, c, s);
+}
+
+bool tuning_enabled() {
+    const char* e = getenv("WEO_TUNE");
+    return !(e && e[0] == '0');
+}
+
+bool tuning_verbose() {
+    const char* e = getenv("WEO_TUNE_VERBOSE");
+    return e && e[0] == '1';
+}
+
+hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return hipErrorUnknown;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return hipErrorUnknown; }
+    best->us = 1e30f;
+    best->cfg = {1, 0, 0};
+    hipError_t err = hipSuccess;
+    for (const MrhsCfg& c : candidates(h)) {
+        if ((err = run_cfg(h, c, s)) != hipSuccess) break;       // warm-up
+        (void)hipEventRecord(e0, s);
+        const int reps = 3;
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = run_cfg(h, c, s);
+        (void)hipEventRecord(e1, s);
+        if (err != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const float us = 1000.f * ms / reps;
+        if (tuning_verbose())
+            fprintf(stderr, "[weo tune] fmt %d nrhs %d: nr %d sites %d persist %d -> %.1f us\n", h.fmt, h.nrhs,
+                    c.nr, c.s, c.persist, us);
+        if (us < best->us) { best->us = us; best->cfg = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return err;
+}
+
+}  // namespace
+
+// Forced shape (weo_set_mrhs_shape); nr == 0 means autotune.
+static MrhsCfg g_forced = {0, 0, 0};
+
+int set_mrhs_shape(int nr, int sites, int persist) {
+    if (nr == 0 || nr == 1) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_forced = {nr, 0, 0};
+        return 0;
+    }
+    if (nr != 2 && nr != 3 && nr != 4 && nr != 6) return -1;
+    if (sites != 64 && sites != 128 && sites != 256) return -1;
+    if (persist != 0 && persist != 1) return -1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_forced = {nr, sites, persist};
+    return 0;
+}
+
+hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
+    if (h.nrhs == 1) return launch_hop_single(h, s);
+    MrhsCfg forced;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        forced = g_forced;
+    }
+    if (forced.nr == 1) return launch_hop_single(h, s);
+    if (forced.nr > 1) {
+        MrhsCfg c = forced;
+        const bool wide = fmt_info(h.fmt).spinor_prec == P_F64;
+        if (wide && c.nr > 3) c.nr = 3;          // FP64 builds nr 2 and 3 only
+        if (c.nr > h.nrhs) c.nr = h.nrhs;
+        return c.nr <= 1 ? launch_hop_single(h, s) : launch_hop_mrhs(h, c, s);
+    }
+    const TuneKey key{h.g.lx, h.g.ly, h.g.lz, h.g.lt, h.fmt, h.nrhs};
+    TuneEntry e;
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) { e = it->second; have = true; }
+    }
+    if (!have) {
+        if (tuning_enabled()) {
+            const hipError_t err = tune(h, s, &e);
+            if (err != hipSuccess) return err;
+        } else {
+            e.cfg = {h.nrhs >= 3 ? 3 : h.nrhs, 64, 0};
+            e.us = 0.f;
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = e;
+    }
+    return run_cfg(h, e.cfg, s);
+}
+
+// Text report of the tuned choices (one line per key) for diagnostics.
+int tuning_report(char* buf, size_t len) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    size_t off = 0;
+    for (const auto& kv : g_tune) {
+        const TuneKey& k = kv.first;
+        const TuneEntry& e = kv.second;
+        const int n = snprintf(buf ? buf + off : nullptr, buf && off < len ? len - off : 0,
+                               "{\"dims\":[%d,%d,%d,%d],\"fmt\":%d,\"nrhs\":%d,\"nr\":%d,\"sites\":%d,"
+                               "\"persist\":%d,\"us\":%.2f}\n",
+                               std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                               std::get<5>(k), e.cfg.nr, e.cfg.s, e.cfg.persist, e.us);
+        if (n > 0) off += (size_t)n;
+    }
+    return (int)off;
+}
+
+}  // namespace weo

@@ -190,7 +190,7 @@ int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const
     // the residual doubles as the operator input when both are stored alike
     const bool same = fmt_info(fmt_op).spinor_prec == fmt_info(fmt_acc).spinor_prec;
     void* s_op = same ? w.s_acc : w.s_op;
-    const uint32_t nbh = hop_blocks(g, nrhs), nbb = blas_blocks(g);
+    const uint32_t nbh = hop_partials(g), nbb = blas_blocks(g);
     ScalarArgsHost sa = sargs(w.sc, nrhs);
     res->iters = 0;
     res->breakdown = 0;

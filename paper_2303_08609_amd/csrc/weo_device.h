@@ -324,6 +324,13 @@ __host__ __device__ __forceinline__ Nbr neighbours(const Geom& g, const Site& s)
     return n;
 }
 
+// Sum over the 64 lanes of a wavefront (result in every lane).
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // Workgroup index remap: the hardware deals consecutive workgroups round-robin
 // to the 8 XCDs (each with its own L2).  Map them so that XCD k works on one
 // contiguous range of the lattice, keeping stencil neighbours in one L2.

@@ -41,7 +41,7 @@ struct HopLaunch {
     void* out;
     const void* y;
     double alpha;
-    double* partial;      // [nrhs][hop_blocks()] or nullptr
+    double* partial;      // [nrhs][hop_partials()] or nullptr: one per 64 sites
     int nrhs;
 };
 
@@ -51,8 +51,18 @@ struct TuneCfg {
     int rhs_grp;  // multi-rhs: rhs handled per thread (divides the tile)
 };
 TuneCfg& hop_tune();                       // current single-rhs launch shape
-uint32_t hop_blocks(const Geom& g, int nrhs);
-hipError_t launch_hop(const HopLaunch& h, hipStream_t s);
+uint32_t hop_partials(const Geom& g);      // norm partials per rhs: one per 64 sites
+hipError_t launch_hop(const HopLaunch& h, hipStream_t s);          // picks the kernel
+hipError_t launch_hop_single(const HopLaunch& h, hipStream_t s);   // one lane per site
+// Multi-rhs kernel: one lane per (site, group of nr rhs); links are loaded
+// once per lane and applied to its nr right-hand sides.  s = sites per
+// workgroup (64, 128 or 256), up to 256 / s rhs groups per workgroup and the
+// rest in grid rows; persist = 1: a grid of min(#blocks, 8 * 256) workgroups
+// (a multiple of 8) looping over site blocks.
+struct MrhsCfg { int nr, s, persist; };
+hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t st);
+int set_mrhs_shape(int nr, int sites, int persist);   // 0 ok, -1 bad value
+int tuning_report(char* buf, size_t len);             // JSON lines, returns length
 
 // ---- BLAS-1 on packed spinor fields (one parity, nrhs fields) -------------
 // Scalars live in device memory (double) so the solver never needs the host

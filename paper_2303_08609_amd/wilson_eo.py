@@ -55,6 +55,8 @@ _SIGS = {
     "wilson_eo_strerror": (C.c_char_p, [C.c_int]),
     "weo_selftest": (C.c_int, []),
     "weo_format_supported": (C.c_int, [_P(weo_format)]),
+    "weo_set_mrhs_shape": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+    "weo_tuning_report": (C.c_int, [C.c_char_p, C.c_size_t]),
     "weo_gauge_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format)]),
     "weo_spinor_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format), C.c_int]),
     "weo_pack_gauge": (C.c_int, [_P(weo_lattice), _P(weo_format), _vp, C.c_int, _vp, _vp]),
@@ -122,6 +124,15 @@ def _call(name):
 
 weo_selftest = _call("weo_selftest")
 weo_format_supported = _call("weo_format_supported")
+weo_set_mrhs_shape = _call("weo_set_mrhs_shape")
+weo_tuning_report = _call("weo_tuning_report")
+
+
+def tuning_report() -> str:
+    n = weo_tuning_report(None, 0)
+    buf = C.create_string_buffer(n + 1)
+    weo_tuning_report(buf, n + 1)
+    return buf.value.decode()
 weo_gauge_bytes = _call("weo_gauge_bytes")
 weo_spinor_bytes = _call("weo_spinor_bytes")
 weo_pack_gauge = _call("weo_pack_gauge")

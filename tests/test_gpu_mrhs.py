@@ -1,0 +1,70 @@
+"""Multi right-hand-side hops against the oracle, for every launch shape the
+autotuner can pick (forced one at a time) and for the tuned choice: 12
+sources, several formats, a ragged lattice, both parities and dagger."""
+import numpy as np
+import pytest
+
+from oracle import wilson as W
+from paper_2303_08609_amd import inputs
+from paper_2303_08609_amd import wilson_eo as WE
+from paper_2303_08609_amd.ops import Format, Lattice, to_device
+from tests._helpers import AP, ROUND, link_as_stored, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-6, "f16": 2e-3, "bf16": 1e-2}
+SHAPES = [(1, 0, 0)] + [(nr, s, p) for nr in (2, 3, 4, 6) for s in (64, 128, 256) for p in (0, 1)]
+
+
+def _setup(dims, fmt_t, nrhs, seed=700):
+    sp, lp, reals = fmt_t
+    fmt = Format(sp, lp, reals)
+    lat = Lattice(dims, 0.126, AP)
+    u = inputs.gen_gauge(dims, 0.5, seed)
+    psi = inputs.gen_spinor_half(dims, seed + 1, nrhs=nrhs)
+    return (lat, fmt, lat.pack_gauge(to_device(u), fmt), lat.pack_spinor(to_device(psi), fmt),
+            link_as_stored(u, lp, reals), ROUND[sp](psi))
+
+
+@pytest.fixture(autouse=True)
+def _reset_shape():
+    yield
+    WE.weo_set_mrhs_shape(0, 0, 0)
+
+
+@pytest.mark.parametrize("fmt_t", [("f32", "f32", 18), ("f64", "f64", 12), ("bf16", "f16", 12)],
+                         ids=["f32-18", "f64-12", "bf16-12"])
+def test_every_shape_matches_oracle(fmt_t):
+    dims, nrhs = (6, 4, 4, 10), 12          # V/2 = 480: ragged last workgroup
+    print(f"mrhs shapes fmt={fmt_t}", flush=True)
+    lat, fmt, u_d, x_d, u_o, psi_o = _setup(dims, fmt_t, nrhs)
+    ph = np.array(AP, dtype=np.complex128)
+    want = [W.hop_eo(u_o, psi_o[r], 0, ph) for r in range(nrhs)]
+    want_dag = [W.hop_eo(u_o, psi_o[r], 0, ph, dagger=True) for r in range(nrhs)]
+    for shape in SHAPES:
+        assert WE.weo_set_mrhs_shape(*shape) == WE.WEO_OK
+        for dag, ref in ((False, want), (True, want_dag)):
+            out = lat.hop(u_d, x_d, fmt, out_parity=1, dagger=dag, nrhs=nrhs)
+            got = lat.unpack_spinor(out, fmt, nrhs=nrhs).cpu().numpy()
+            for r in range(nrhs):
+                assert rel_err(got[r], ref[r]) <= TOL[fmt_t[0]], (shape, dag, r)
+
+
+@pytest.mark.parametrize("nrhs", [2, 5, 12, 16])
+def test_tuned_apply_matches_oracle(nrhs):
+    dims = (8, 4, 6, 4)
+    print(f"mrhs tuned apply nrhs={nrhs}", flush=True)
+    lat, fmt, u_d, x_d, u_o, psi_o = _setup(dims, ("f32", "f32", 12), nrhs, seed=710)
+    WE.weo_set_mrhs_shape(0, 0, 0)
+    out = lat.apply(u_d, x_d, fmt, nrhs=nrhs)
+    got = lat.unpack_spinor(out, fmt, nrhs=nrhs).cpu().numpy()
+    ph = np.array(AP, dtype=np.complex128)
+    for r in range(nrhs):
+        assert rel_err(got[r], W.apply_m(u_o, psi_o[r], lat.kappa, ph)) <= 1e-6
+    assert '"nrhs":%d' % nrhs in WE.tuning_report()
+
+
+def test_bad_shape_rejected():
+    assert WE.weo_set_mrhs_shape(5, 64, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(2, 96, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(2, 64, 2) == WE.WEO_ERR_ARG
