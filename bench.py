@@ -13,10 +13,14 @@ The JSON line also carries:
   cpu_baseline  the FP64 NumPy oracle timed on a sample of the same workload
                 on this host (single thread);
   variants      the same apply in other storage formats;
-  solve         solver results when --solve is given.
+  solve         solve times to a true FP64 residual of 1e-10 (and FP32 CGLS to
+                1e-6): FP64 defect correction with FP16/BF16 inner solves
+                against FP32 inner solves, for one source at 32^3x64, twelve
+                point+noise sources at 32^3x64 (batched vs one at a time) and
+                one source at 48^3x96.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--format f32/f32/18]
-                    [--solve] [--no-cpu]
+                    [--no-solve] [--no-cpu] [--profile-mode]
 """
 from __future__ import annotations
 
@@ -61,7 +65,7 @@ def apply_bytes_per_site(sp, lp, reals):
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2303_08609_amd", "csrc")
-    for f in ("hop.hip", "weo_device.h", "weo_geom.h"):
+    for f in ("hop.hip", "hop_core.h", "weo_device.h", "weo_geom.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -114,7 +118,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--format", default="f32/f32/18")
     ap.add_argument("--variants", default="f32/f32/12,f64/f64/18,f16/f16/12,bf16/f16/12")
-    ap.add_argument("--solve", action="store_true")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the solver timings (32^3x64 single and 12 rhs, 48^3x96)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-mode", action="store_true",
                     help="short fixed run for rocprofv3: a 1 GiB device copy (counter "
@@ -212,9 +217,17 @@ def main():
         print(f"[bench] {vs}: {variants[vs]}", file=sys.stderr, flush=True)
 
     solve = None
-    if a.solve:
+    if not a.no_solve:
         from paper_2303_08609_amd import solve as S
-        solve = S.bench_solves(lat, u, psi, u_dev64, psi_dev64)
+        solve = {"32^3x64_single_rhs": S.bench_solves(lat, u, psi, u_dev64, psi_dev64)}
+        print(f"[bench] single-rhs solves: {solve}", file=sys.stderr, flush=True)
+        del u_dev64, psi_dev64
+        torch.cuda.empty_cache()
+        solve["32^3x64_12rhs_point_noise"] = S.bench_solves_12rhs()
+        print(f"[bench] 12-rhs solves: {solve['32^3x64_12rhs_point_noise']}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        solve["48^3x96_mixed"] = S.bench_solves_large()
+        print(f"[bench] 48^3x96 solves: {solve['48^3x96_mixed']}", file=sys.stderr, flush=True)
 
     line = {
         "metric": "eo-Wilson GFlop/s + % HBM roofline (32^3x64); mixed vs FP32 solve time",

@@ -2,8 +2,8 @@
 
 ``cg`` solves M x = b (CGLS) or M^dag M x = b (CG) for 1..16 packed right-hand
 sides, either in one format or as FP64 defect correction around inner solves
-in a low-precision format.  ``bench_solves`` times the solves the benchmark
-reports.
+in a low-precision format.  ``bench_solves``, ``bench_solves_12rhs`` and
+``bench_solves_large`` time the solves the benchmark reports.
 """
 from __future__ import annotations
 
@@ -99,5 +99,104 @@ def bench_solves(lat: Lattice, u_np, psi_np, u_dev64, psi_dev64, reps=1):
         del ui
     base = out["dc_fp32_1e-10"]["seconds"]
     for k in ("dc_bf16_f16link12_1e-10", "dc_f16_f16link12_1e-10"):
+        out[k]["speedup_vs_fp32_inner"] = round(base / out[k]["seconds"], 3)
+    return out
+
+
+def _timed(fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, res
+
+
+def bench_solves_12rhs(dims=(32, 32, 32, 64), kappa=0.126, eps=0.5, seed_gauge=401, seed_noise=406):
+    """12 sources (a point source per spin x colour plus Gaussian noise) to a
+    true FP64 residual of 1e-10 each:
+    * plain FP32 path: FP64 defect correction with FP32 (18-real) inner
+      solves, one right-hand side after the other;
+    * batched mixed path: the 12 sources in one solve, FP64 defect correction
+      around batched inner solves with FP16 / BF16 spinors and FP16 12-real
+      links (inner tolerance 1e-3).
+    Links are packed before timing; each timed path runs once untimed first
+    (kernel loading, multi-rhs shape tuning)."""
+    from . import inputs
+    lat = Lattice(dims, kappa, (1, 1, 1, -1))
+    u = inputs.gen_gauge(dims, eps, seed_gauge)
+    b = inputs.gen_point_noise_sources(dims, seed_noise)
+    ud = torch.from_numpy(u).cuda()
+    bd = torch.from_numpy(b).cuda()
+    del u, b
+    f64 = Format("f64", "f64", 18)
+    u64 = lat.pack_gauge(ud, f64)
+    b64 = lat.pack_spinor(bd, f64)
+    fsize = lat.spinor_bytes(f64)
+    out = {}
+    # plain FP32 inner, one rhs at a time
+    f32 = Format("f32", "f32", 18)
+    u32 = lat.pack_gauge(ud, f32)
+    total, worst, iters = 0.0, 0.0, 0
+    cg(lat, f64, u64, b64[:fsize], tol=1e-10, inner=f32, u_inner=u32, inner_tol=1e-5,
+       maxiter=50000, max_outer=100)                           # untimed warm-up
+    for r in range(12):
+        br = b64[r * fsize:(r + 1) * fsize]
+        dt, (x, info) = _timed(lambda: cg(lat, f64, u64, br, tol=1e-10, inner=f32, u_inner=u32,
+                                          inner_tol=1e-5, maxiter=50000, max_outer=100))
+        total += dt
+        worst = max(worst, info["true_rel_resid"][0])
+        iters += info["iters"]
+    out["fp32_inner_sequential"] = {"seconds": round(total, 4), "inner_iters": iters,
+                                    "worst_true_rel_resid": worst}
+    del u32
+    for name, inner in (("f16_f16link12", Format("f16", "f16", 12)),
+                        ("bf16_f16link12", Format("bf16", "f16", 12)),
+                        ("fp32", Format("f32", "f32", 18))):
+        ui = lat.pack_gauge(ud, inner)
+        tol_in = 1e-5 if name == "fp32" else 1e-3
+        cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=inner, u_inner=ui, inner_tol=tol_in,
+           maxiter=50000, max_outer=100)                   # first call tunes the hop shapes
+        dt, (x, info) = _timed(lambda: cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=inner,
+                                          u_inner=ui, inner_tol=tol_in, maxiter=50000,
+                                          max_outer=100))
+        out[f"batched12_{name}"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
+                                    "outer_iters": info["outer_iters"],
+                                    "worst_true_rel_resid": max(info["true_rel_resid"]),
+                                    "status": info["status"]}
+        del ui
+    base = out["fp32_inner_sequential"]["seconds"]
+    for k in list(out):
+        if k.startswith("batched12"):
+            out[k]["speedup_vs_fp32_sequential"] = round(base / out[k]["seconds"], 3)
+    return out
+
+
+def bench_solves_large(dims=(48, 48, 48, 96), kappa=0.1265, eps=0.7, seed_gauge=301, seed_src=302):
+    """One Gaussian source on 48^3x96 to a true FP64 residual of 1e-10: FP64
+    defect correction around FP16 / BF16 spinor + FP16 12-real link inner
+    solves (inner tolerance 1e-3), against the same driver with FP32 inner
+    solves."""
+    from . import inputs
+    lat = Lattice(dims, kappa, (1, 1, 1, -1))
+    u = inputs.gen_gauge(dims, eps, seed_gauge)
+    ud = torch.from_numpy(u).cuda()
+    del u
+    bd = torch.from_numpy(inputs.gen_spinor_half(dims, seed_src)).cuda()
+    f64 = Format("f64", "f64", 18)
+    u64 = lat.pack_gauge(ud, f64)
+    b64 = lat.pack_spinor(bd, f64)
+    out = {}
+    for name, inner in (("fp32", Format("f32", "f32", 18)), ("f16_f16link12", Format("f16", "f16", 12)),
+                        ("bf16_f16link12", Format("bf16", "f16", 12))):
+        ui = lat.pack_gauge(ud, inner)
+        tol_in = 1e-5 if name == "fp32" else 1e-3
+        dt, (x, info) = _timed(lambda: cg(lat, f64, u64, b64, tol=1e-10, inner=inner, u_inner=ui,
+                                          inner_tol=tol_in, maxiter=50000, max_outer=100))
+        out[f"dc_{name}"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
+                             "outer_iters": info["outer_iters"],
+                             "true_rel_resid_fp64": info["true_rel_resid"][0], "status": info["status"]}
+        del ui
+    base = out["dc_fp32"]["seconds"]
+    for k in ("dc_f16_f16link12", "dc_bf16_f16link12"):
         out[k]["speedup_vs_fp32_inner"] = round(base / out[k]["seconds"], 3)
     return out
