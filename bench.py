@@ -190,6 +190,19 @@ def main():
             torch.cuda.synchronize()
             print(f"[bench] profiled {a.steps} hop launches of {vs}", file=sys.stderr, flush=True)
             del ud, xd, tmp
+        # twelve right-hand sides through the multi-rhs kernel (tuned shape)
+        b12 = torch.from_numpy(inputs.gen_point_noise_sources(DIMS, 406)).cuda()
+        for vs in ("f32/f32/18", "f16/f16/12"):
+            f2 = Format(*parse_fmt(vs))
+            ud = lat.pack_gauge(u_dev64, f2)
+            xd = lat.pack_spinor(b12, f2)
+            tmp = lat.new_spinor(f2, 12)
+            lat.hop(ud, xd, f2, out_parity=1, nrhs=12, out=tmp)         # tunes the shape
+            for _ in range(a.steps):
+                lat.hop(ud, xd, f2, out_parity=1, nrhs=12, out=tmp)
+            torch.cuda.synchronize()
+            print(f"[bench] profiled {a.steps} 12-rhs hop launches of {vs}", file=sys.stderr, flush=True)
+            del ud, xd, tmp
         return
 
     fs = parse_fmt(a.format)

@@ -16,7 +16,7 @@ __global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_ho
     using R = typename Arith<SP>::R;
     using C = cx<R>;
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x, P.remap);
-    const uint32_t ih = blk * blockDim.x + threadIdx.x;
+    const uint32_t ih = block_first_site(P.sched, P.g, blk, blockDim.x) + threadIdx.x;
     const int rhs = blockIdx.y;
     const uint8_t* in = P.in + (size_t)rhs * P.spinor_bytes;
     uint8_t* out = P.out + (size_t)rhs * P.spinor_bytes;
@@ -66,17 +66,18 @@ __global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_ho
     if constexpr (NORM) {
         // one partial per 64-site chunk (one wavefront)
         const double s = wave_sum64(nrm);
-        const uint32_t chunk = (blk * blockDim.x + (threadIdx.x & ~63u)) >> 6;
+        const uint32_t chunk = (block_first_site(P.sched, P.g, blk, blockDim.x) + (threadIdx.x & ~63u)) >> 6;
         const uint32_t nchunk = (P.g.vh + 63) >> 6;
         if ((threadIdx.x & 63) == 0 && chunk < nchunk) P.partial[(size_t)rhs * nchunk + chunk] = s;
     }
 }
 
 // ------------------------------------------------------------------ host ----
-static TuneCfg g_hop_tune = {256, 1, 1};
+static TuneCfg g_hop_tune = {256, 1, 0};
 TuneCfg& hop_tune() { return g_hop_tune; }
 
-// Launch-shape overrides from the environment (WEO_HOP_BLOCK, WEO_HOP_REMAP),
+// Launch-shape overrides from the environment (WEO_HOP_BLOCK, WEO_HOP_REMAP,
+// WEO_HOP_BZ),
 // read once; values outside the legal range are ignored.
 static void read_env_tuning() {
     static bool done = false;
@@ -87,6 +88,10 @@ static void read_env_tuning() {
         if (v >= 64 && v <= 256 && v % 64 == 0) g_hop_tune.block = v;
     }
     if (const char* r = getenv("WEO_HOP_REMAP")) g_hop_tune.remap = atoi(r) ? 1 : 0;
+    if (const char* z = getenv("WEO_HOP_BZ")) {
+        const int v = atoi(z);
+        if (v >= 0 && v <= 64) g_hop_tune.bz = v;
+    }
 }
 
 uint32_t hop_partials(const Geom& g) { return (g.vh + 63) / 64; }
@@ -132,6 +137,7 @@ hipError_t launch_hop_single(const HopLaunch& h, hipStream_t s) {
     P.partial = h.partial;
     P.spinor_bytes = spinor_field_bytes(h.g, h.fmt);
     P.link_block = gauge_block_bytes(h.g, h.fmt);
+    P.sched = make_sched(h.g, g_hop_tune.bz, (uint32_t)g_hop_tune.block);
     const dim3 block(g_hop_tune.block);
     const dim3 grid(hop_blocks(h.g), h.nrhs);
     switch (h.fmt) {

@@ -77,6 +77,7 @@ struct HopParams {
     double* partial;
     size_t spinor_bytes;    // bytes of one packed spinor field
     size_t link_block;      // bytes of one (mu, parity) link block
+    Sched sched;            // workgroup -> sites order
 };
 
 // Link U as 9 complex numbers (row-major); a 12-real record is completed with

@@ -18,7 +18,9 @@
 // The launch shape (NR, sites per workgroup, persistence) is picked per
 // (lattice, format, nrhs) by timing every candidate on the first call with
 // that key on the caller's stream and buffers (one stream synchronisation),
-// then cached for the life of the process.  WEO_TUNE=0 in the environment
+// then cached for the life of the process.  The candidates also cover the
+// workgroup schedule (z-strips of 2, 4 or 8 planes, make_sched), which keeps
+// the +-t neighbours of 12 fields inside L2.  WEO_TUNE=0 in the environment
 // disables the search and uses NR = 3, 64 sites, no persistence.
 #include <stdio.h>
 #include <stdlib.h>
@@ -127,7 +129,8 @@ __global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
     const uint32_t nchunk = (P.g.vh + 63) >> 6;
     for (uint32_t b = blockIdx.x; b < M.nblk; b += gridDim.x) {
         const uint32_t blk = xcd_block(b, M.nblk, P.remap);
-        const uint32_t ih = blk * S + threadIdx.x;
+        const uint32_t base = block_first_site(P.sched, P.g, blk, S);
+        const uint32_t ih = base + threadIdx.x;
         double nrm[NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) nrm[q] = 0.0;
@@ -183,7 +186,7 @@ __global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
             }
         }
         if (P.partial) {
-            const uint32_t chunk = (blk * S + (threadIdx.x & ~63u)) >> 6;
+            const uint32_t chunk = (base + (threadIdx.x & ~63u)) >> 6;
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
                 const double t = wave_sum64(nrm[q]);
@@ -242,6 +245,7 @@ static hipError_t mrhs_fmt(const HopLaunch& h, const MrhsParams& M, int nr, dim3
 hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) {
     MrhsParams M;
     M.h = hop_params(h);
+    M.h.sched = make_sched(h.g, c.bz, (uint32_t)c.s);
     M.nrhs = h.nrhs;
     M.nblk = (h.g.vh + (uint32_t)c.s - 1) / (uint32_t)c.s;
     const int groups = (h.nrhs + c.nr - 1) / c.nr;
@@ -282,13 +286,17 @@ std::map<TuneKey, TuneEntry> g_tune;
 
 std::vector<MrhsCfg> candidates(const HopLaunch& h) {
     std::vector<MrhsCfg> v;
-    v.push_back({1, 0, 0});
+    v.push_back({1, 0, 0, 0});
     const bool wide = fmt_info(h.fmt).spinor_prec == P_F64;
     const int nrs[] = {2, 3, 4, 6};
     for (int nr : nrs) {
         if (nr > h.nrhs || (wide && nr > 3)) continue;
         for (int s : {64, 128, 256})
-            for (int persist : {0, 1}) v.push_back({nr, s, persist});
+            for (int persist : {0, 1})
+                for (int bz : {0, 2, 4, 8}) {
+                    if (bz && make_sched(h.g, bz, (uint32_t)s).bz != bz) continue;
+                    v.push_back({nr, s, persist, bz});
+                }
     }
     return v;
 }
@@ -312,7 +320,7 @@ hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
     if (hipEventCreate(&e0) != hipSuccess) return hipErrorUnknown;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return hipErrorUnknown; }
     best->us = 1e30f;
-    best->cfg = {1, 0, 0};
+    best->cfg = {1, 0, 0, 0};
     hipError_t err = hipSuccess;
     for (const MrhsCfg& c : candidates(h)) {
         if ((err = run_cfg(h, c, s)) != hipSuccess) break;       // warm-up
@@ -325,8 +333,8 @@ hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
         (void)hipEventElapsedTime(&ms, e0, e1);
         const float us = 1000.f * ms / reps;
         if (tuning_verbose())
-            fprintf(stderr, "[weo tune] fmt %d nrhs %d: nr %d sites %d persist %d -> %.1f us\n", h.fmt, h.nrhs,
-                    c.nr, c.s, c.persist, us);
+            fprintf(stderr, "[weo tune] fmt %d nrhs %d: nr %d sites %d persist %d bz %d -> %.1f us\n", h.fmt,
+                    h.nrhs, c.nr, c.s, c.persist, c.bz, us);
         if (us < best->us) { best->us = us; best->cfg = c; }
     }
     (void)hipEventDestroy(e0);
@@ -337,19 +345,20 @@ hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
 }  // namespace
 
 // Forced shape (weo_set_mrhs_shape); nr == 0 means autotune.
-static MrhsCfg g_forced = {0, 0, 0};
+static MrhsCfg g_forced = {0, 0, 0, 0};
 
-int set_mrhs_shape(int nr, int sites, int persist) {
+int set_mrhs_shape(int nr, int sites, int persist, int bz) {
     if (nr == 0 || nr == 1) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_forced = {nr, 0, 0};
+        g_forced = {nr, 0, 0, 0};
         return 0;
     }
     if (nr != 2 && nr != 3 && nr != 4 && nr != 6) return -1;
     if (sites != 64 && sites != 128 && sites != 256) return -1;
     if (persist != 0 && persist != 1) return -1;
+    if (bz < 0 || bz > 64) return -1;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_forced = {nr, sites, persist};
+    g_forced = {nr, sites, persist, bz};
     return 0;
 }
 
@@ -381,7 +390,7 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
             const hipError_t err = tune(h, s, &e);
             if (err != hipSuccess) return err;
         } else {
-            e.cfg = {h.nrhs >= 3 ? 3 : h.nrhs, 64, 0};
+            e.cfg = {h.nrhs >= 3 ? 3 : h.nrhs, 64, 0, 0};
             e.us = 0.f;
         }
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -399,9 +408,9 @@ int tuning_report(char* buf, size_t len) {
         const TuneEntry& e = kv.second;
         const int n = snprintf(buf ? buf + off : nullptr, buf && off < len ? len - off : 0,
                                "{\"dims\":[%d,%d,%d,%d],\"fmt\":%d,\"nrhs\":%d,\"nr\":%d,\"sites\":%d,"
-                               "\"persist\":%d,\"us\":%.2f}\n",
+                               "\"persist\":%d,\"bz\":%d,\"us\":%.2f}\n",
                                std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
-                               std::get<5>(k), e.cfg.nr, e.cfg.s, e.cfg.persist, e.us);
+                               std::get<5>(k), e.cfg.nr, e.cfg.s, e.cfg.persist, e.cfg.bz, e.us);
         if (n > 0) off += (size_t)n;
     }
     return (int)off;

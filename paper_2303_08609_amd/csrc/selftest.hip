@@ -65,6 +65,34 @@ static int check_remap() {
     return 0;
 }
 
+// Every site is visited exactly once under each workgroup schedule.
+static int check_sched(const int dims[4]) {
+    const Geom g = make_geom(dims);
+    for (uint32_t S : {64u, 128u, 256u}) {
+        for (int bz : {0, 2, 4, 8}) {
+            const Sched sc = make_sched(g, bz, S);
+            if (bz && sc.bz == 0) continue;
+            const uint32_t nblk = (g.vh + S - 1) / S;
+            std::vector<char> seen(g.vh, 0);
+            for (uint32_t b = 0; b < nblk; ++b) {
+                const uint32_t f = block_first_site(sc, g, b, S);
+                for (uint32_t t = 0; t < S; ++t) {
+                    const uint32_t ih = f + t;
+                    if (ih >= g.vh) {
+                        if (sc.bz) return 31;     // blocked schedules have no ragged tail
+                        continue;
+                    }
+                    if (seen[ih]) return 30;
+                    seen[ih] = 1;
+                }
+            }
+            for (uint32_t i = 0; i < g.vh; ++i)
+                if (!seen[i]) return 32;
+        }
+    }
+    return 0;
+}
+
 }  // namespace weo
 
 extern "C" int weo_selftest(void) {
@@ -76,5 +104,7 @@ extern "C" int weo_selftest(void) {
                              {48, 48, 48, 96}};
     for (const auto& d : shapes)
         if ((rc = check_geometry(d))) return rc;
+    for (const auto& d : shapes)
+        if ((rc = check_sched(d))) return rc;
     return check_remap();
 }

@@ -324,6 +324,28 @@ __host__ __device__ __forceinline__ Nbr neighbours(const Geom& g, const Site& s)
     return n;
 }
 
+// Order in which workgroups visit the lattice.  bz = 0: lexicographic
+// (x fastest, then y, z, t).  bz > 0: the (z, t) planes are visited in
+// strips of bz consecutive z values, all t for one strip before the next
+// strip, so the input records a site shares with its +-t neighbours are
+// touched again within a window of about bz planes instead of a whole
+// t-slice (this matters when many right-hand sides multiply the working set).
+// Needs plane % S == 0 (S = sites per workgroup) and lz % bz == 0.
+using Sched = SchedHost;    // built on the host by make_sched (weo_geom.h)
+
+__host__ __device__ __forceinline__ uint32_t block_first_site(const Sched& s, const Geom& g, uint32_t blk,
+                                                              uint32_t S) {
+    if (s.bz == 0) return blk * S;
+    const uint32_t q = fdiv(blk, s.d_bpp);
+    const uint32_t c = blk - q * s.d_bpp.d;
+    const uint32_t q2 = fdiv(q, s.d_bz);
+    const uint32_t zi = q - q2 * s.d_bz.d;
+    const uint32_t zb = fdiv(q2, s.d_lt);
+    const uint32_t t = q2 - zb * s.d_lt.d;
+    const uint32_t z = zb * s.d_bz.d + zi;
+    return c * S + s.plane * (z + (uint32_t)g.lz * t);
+}
+
 // Sum over the 64 lanes of a wavefront (result in every lane).
 __device__ __forceinline__ double wave_sum64(double v) {
 #pragma unroll

@@ -51,6 +51,25 @@ inline Geom make_geom(const int dims[4]) {
     return g;
 }
 
+// Schedule descriptor for block_first_site (weo_device.h); bz = 0 when the
+// requested strip height does not fit the lattice or the workgroup size.
+struct SchedHost {
+    int bz;
+    uint32_t plane;
+    FastDiv d_bpp, d_bz, d_lt;
+};
+
+inline SchedHost make_sched(const Geom& g, int bz, uint32_t sites_per_block) {
+    SchedHost s;
+    s.plane = (uint32_t)g.lxh * (uint32_t)g.ly;
+    s.bz = 0;
+    if (bz > 0 && sites_per_block > 0 && s.plane % sites_per_block == 0 && g.lz % bz == 0) s.bz = bz;
+    s.d_bpp = make_fastdiv(s.bz ? s.plane / sites_per_block : 1);
+    s.d_bz = make_fastdiv(s.bz ? (uint32_t)s.bz : 1);
+    s.d_lt = make_fastdiv((uint32_t)g.lt);
+    return s;
+}
+
 // Built storage formats.  id = 2 * combo + (link12 ? 1 : 0).
 enum FmtId : int {
     FMT_D_D_18 = 0, FMT_D_D_12 = 1,     // F64 spinor, F64 links

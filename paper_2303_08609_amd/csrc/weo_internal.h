@@ -46,9 +46,9 @@ struct HopLaunch {
 };
 
 struct TuneCfg {
-    int block;    // threads per workgroup (multiple of 64, <= 1024)
+    int block;    // threads per workgroup (multiple of 64, <= 256)
     int remap;    // XCD-aware workgroup remap on/off
-    int rhs_grp;  // multi-rhs: rhs handled per thread (divides the tile)
+    int bz;       // workgroup schedule: z-strip height (0 = lexicographic)
 };
 TuneCfg& hop_tune();                       // current single-rhs launch shape
 uint32_t hop_partials(const Geom& g);      // norm partials per rhs: one per 64 sites
@@ -59,9 +59,9 @@ hipError_t launch_hop_single(const HopLaunch& h, hipStream_t s);   // one lane p
 // workgroup (64, 128 or 256), up to 256 / s rhs groups per workgroup and the
 // rest in grid rows; persist = 1: a grid of min(#blocks, 8 * 256) workgroups
 // (a multiple of 8) looping over site blocks.
-struct MrhsCfg { int nr, s, persist; };
+struct MrhsCfg { int nr, s, persist, bz; };
 hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t st);
-int set_mrhs_shape(int nr, int sites, int persist);   // 0 ok, -1 bad value
+int set_mrhs_shape(int nr, int sites, int persist, int bz);   // 0 ok, -1 bad value
 int tuning_report(char* buf, size_t len);             // JSON lines, returns length
 
 // ---- BLAS-1 on packed spinor fields (one parity, nrhs fields) -------------
