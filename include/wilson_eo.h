@@ -111,12 +111,13 @@ int weo_format_supported(const weo_format* fmt);
  * nrhs) -- on the caller's stream and buffers, with one stream
  * synchronisation -- and caches the fastest for the process.  nr = 1: one
  * lane per (site, rhs).  nr in {2, 3, 4, 6} (FP64 uses at most 3) with
- * sites per workgroup in {64, 128, 256}, persist in {0, 1} and bz in 0..64
- * forces that shape.  bz > 0 visits the lattice in strips of bz z-planes,
- * all t per strip (ignored where the lattice or workgroup size does not
- * allow it).  Returns WEO_ERR_ARG for other values.  The setting is
- * process-wide. */
-int weo_set_mrhs_shape(int nr, int sites, int persist, int bz);
+ * sites per workgroup in {64, 128, 256}, persist in {0, 1}, bz in 0..64 and
+ * split in {0, 1} forces that shape.  bz > 0 visits the lattice in strips of
+ * bz z-planes, all t per strip (ignored where the lattice or workgroup size
+ * does not allow it); split = 1 gives each group of nr rhs its own
+ * workgroups and sweep of the lattice.  Returns WEO_ERR_ARG for other values.
+ * The setting is process-wide. */
+int weo_set_mrhs_shape(int nr, int sites, int persist, int bz, int split);
 
 /* The autotuner's cached choices as JSON lines in buf (NUL-terminated,
  * truncated to len bytes); returns the untruncated length.  buf may be NULL

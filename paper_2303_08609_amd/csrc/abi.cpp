@@ -113,8 +113,8 @@ const char* wilson_eo_strerror(int code) {
 
 int weo_format_supported(const weo_format* fmt) { return format_id(fmt) >= 0 ? 1 : 0; }
 
-int weo_set_mrhs_shape(int nr, int sites, int persist, int bz) {
-    return set_mrhs_shape(nr, sites, persist, bz) == 0 ? WEO_OK : WEO_ERR_ARG;
+int weo_set_mrhs_shape(int nr, int sites, int persist, int bz, int split) {
+    return set_mrhs_shape(nr, sites, persist, bz, split) == 0 ? WEO_OK : WEO_ERR_ARG;
 }
 
 int weo_tuning_report(char* buf, size_t len) {

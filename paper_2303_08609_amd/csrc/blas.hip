@@ -25,9 +25,10 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum over the workgroup in a fixed order; result in thread 0.
+// Sum over the workgroup (at most 1024 lanes) in a fixed order; result in
+// thread 0.
 __device__ __forceinline__ double group_sum(double v) {
-    __shared__ double lds[kBlk / 64];
+    __shared__ double lds[16];
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -148,7 +149,7 @@ __global__ void __launch_bounds__(kBlk) k_axpby(Fields F, double ca, const uint8
 #pragma unroll
                 for (int k = 0; k < 12; ++k) st[k] = av[k];
             } else {
-                load_rec<P, 12>(out + (size_t)r * F.fb_op, F.vh, i, st);
+                round_rec<P, 12>(av, st);
             }
             nrm = norm2_12(st);
         }
@@ -206,13 +207,18 @@ __global__ void k_zero(uint4* p, size_t n16) {
 }
 
 // out[r] = sum_b partial[r][b] in a fixed order (one workgroup per rhs).
+// The final sums run in one workgroup per rhs; 1024 lanes keep the strided
+// first pass short when there are tens of thousands of partials.
+static constexpr int kRed = 1024;
+
 __device__ __forceinline__ double reduce_row(const double* row, int nb) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlk) v += row[b];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v += row[b];
+    __syncthreads();       // the LDS slots may be reused by a second reduction
     return group_sum(v);
 }
 
-__global__ void __launch_bounds__(kBlk) k_reduce(const double* partial, int nb, double* out) {
+__global__ void __launch_bounds__(kRed) k_reduce(const double* partial, int nb, double* out) {
     const int r = blockIdx.x;
     const double s = reduce_row(partial + (size_t)r * nb, nb);
     if (threadIdx.x == 0) out[r] = s;
@@ -236,7 +242,7 @@ struct ScalarArgs {
     double* nrm;         // SCAL_SCALE: the reduced norm^2
 };
 
-__global__ void __launch_bounds__(kBlk) k_scalars(int kind, ScalarArgs A) {
+__global__ void __launch_bounds__(kRed) k_scalars(int kind, ScalarArgs A) {
     const int r = blockIdx.x;
     const double a = reduce_row(A.pa + (size_t)r * A.nba, A.nba);
     double b = 0.0;
@@ -401,7 +407,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
 }
 
 hipError_t launch_reduce(const double* partial, int nblocks, int nrhs, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(nrhs), dim3(kBlk), 0, st, partial, nblocks, out);
+    hipLaunchKernelGGL(k_reduce, dim3(nrhs), dim3(kRed), 0, st, partial, nblocks, out);
     return hipGetLastError();
 }
 
@@ -411,7 +417,7 @@ hipError_t launch_scalars(int kind, const ScalarArgsHost& h, hipStream_t st) {
     A.gamma = h.gamma; A.alpha = h.alpha; A.beta = h.beta; A.ss = h.ss;
     A.mask = h.mask; A.flags = h.flags; A.target = h.target;
     A.sc_in = h.sc_in; A.sc_out = h.sc_out; A.nrm = h.nrm;
-    hipLaunchKernelGGL(k_scalars, dim3(h.nrhs), dim3(kBlk), 0, st, kind, A);
+    hipLaunchKernelGGL(k_scalars, dim3(h.nrhs), dim3(kRed), 0, st, kind, A);
     return hipGetLastError();
 }
 

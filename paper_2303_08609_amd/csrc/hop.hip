@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_ho
 #pragma unroll
                 for (int k = 0; k < 12; ++k) st[k] = acc[k];
             } else {
-                load_rec<SP, 12>(out, P.g.vh, ih, st);
+                round_rec<SP, 12>(acc, st);
             }
 #pragma unroll
             for (int k = 0; k < 12; ++k)

@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
 #pragma unroll
                             for (int k = 0; k < 12; ++k) st[k] = acc[q][k];
                         } else {
-                            load_rec<SP, 12>(out, P.g.vh, ih, st);
+                            round_rec<SP, 12>(acc[q], st);
                         }
 #pragma unroll
                         for (int k = 0; k < 12; ++k)
@@ -249,7 +249,7 @@ hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) 
     M.nrhs = h.nrhs;
     M.nblk = (h.g.vh + (uint32_t)c.s - 1) / (uint32_t)c.s;
     const int groups = (h.nrhs + c.nr - 1) / c.nr;
-    int gy = 256 / c.s;
+    int gy = c.split ? 1 : 256 / c.s;
     if (gy > groups) gy = groups;
     const dim3 block((unsigned)c.s, (unsigned)gy);
     uint32_t nwg = M.nblk;
@@ -286,7 +286,7 @@ std::map<TuneKey, TuneEntry> g_tune;
 
 std::vector<MrhsCfg> candidates(const HopLaunch& h) {
     std::vector<MrhsCfg> v;
-    v.push_back({1, 0, 0, 0});
+    v.push_back({1, 0, 0, 0, 0});
     const bool wide = fmt_info(h.fmt).spinor_prec == P_F64;
     const int nrs[] = {2, 3, 4, 6};
     for (int nr : nrs) {
@@ -295,7 +295,9 @@ std::vector<MrhsCfg> candidates(const HopLaunch& h) {
             for (int persist : {0, 1})
                 for (int bz : {0, 2, 4, 8}) {
                     if (bz && make_sched(h.g, bz, (uint32_t)s).bz != bz) continue;
-                    v.push_back({nr, s, persist, bz});
+                    v.push_back({nr, s, persist, bz, 0});
+                    const int groups = (h.nrhs + nr - 1) / nr;
+                    if (groups > 1 && s < 256) v.push_back({nr, s, persist, bz, 1});
                 }
     }
     return v;
@@ -320,7 +322,7 @@ hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
     if (hipEventCreate(&e0) != hipSuccess) return hipErrorUnknown;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return hipErrorUnknown; }
     best->us = 1e30f;
-    best->cfg = {1, 0, 0, 0};
+    best->cfg = {1, 0, 0, 0, 0};
     hipError_t err = hipSuccess;
     for (const MrhsCfg& c : candidates(h)) {
         if ((err = run_cfg(h, c, s)) != hipSuccess) break;       // warm-up
@@ -333,8 +335,8 @@ hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
         (void)hipEventElapsedTime(&ms, e0, e1);
         const float us = 1000.f * ms / reps;
         if (tuning_verbose())
-            fprintf(stderr, "[weo tune] fmt %d nrhs %d: nr %d sites %d persist %d bz %d -> %.1f us\n", h.fmt,
-                    h.nrhs, c.nr, c.s, c.persist, c.bz, us);
+            fprintf(stderr, "[weo tune] fmt %d nrhs %d: nr %d sites %d persist %d bz %d split %d -> %.1f us\n",
+                    h.fmt, h.nrhs, c.nr, c.s, c.persist, c.bz, c.split, us);
         if (us < best->us) { best->us = us; best->cfg = c; }
     }
     (void)hipEventDestroy(e0);
@@ -345,20 +347,21 @@ hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
 }  // namespace
 
 // Forced shape (weo_set_mrhs_shape); nr == 0 means autotune.
-static MrhsCfg g_forced = {0, 0, 0, 0};
+static MrhsCfg g_forced = {0, 0, 0, 0, 0};
 
-int set_mrhs_shape(int nr, int sites, int persist, int bz) {
+int set_mrhs_shape(int nr, int sites, int persist, int bz, int split) {
     if (nr == 0 || nr == 1) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_forced = {nr, 0, 0, 0};
+        g_forced = {nr, 0, 0, 0, 0};
         return 0;
     }
+    if (split != 0 && split != 1) return -1;
     if (nr != 2 && nr != 3 && nr != 4 && nr != 6) return -1;
     if (sites != 64 && sites != 128 && sites != 256) return -1;
     if (persist != 0 && persist != 1) return -1;
     if (bz < 0 || bz > 64) return -1;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_forced = {nr, sites, persist, bz};
+    g_forced = {nr, sites, persist, bz, split};
     return 0;
 }
 
@@ -390,7 +393,7 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
             const hipError_t err = tune(h, s, &e);
             if (err != hipSuccess) return err;
         } else {
-            e.cfg = {h.nrhs >= 3 ? 3 : h.nrhs, 64, 0, 0};
+            e.cfg = {h.nrhs >= 3 ? 3 : h.nrhs, 64, 0, 0, 0};
             e.us = 0.f;
         }
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -408,9 +411,9 @@ int tuning_report(char* buf, size_t len) {
         const TuneEntry& e = kv.second;
         const int n = snprintf(buf ? buf + off : nullptr, buf && off < len ? len - off : 0,
                                "{\"dims\":[%d,%d,%d,%d],\"fmt\":%d,\"nrhs\":%d,\"nr\":%d,\"sites\":%d,"
-                               "\"persist\":%d,\"bz\":%d,\"us\":%.2f}\n",
+                               "\"persist\":%d,\"bz\":%d,\"split\":%d,\"us\":%.2f}\n",
                                std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
-                               std::get<5>(k), e.cfg.nr, e.cfg.s, e.cfg.persist, e.cfg.bz, e.us);
+                               std::get<5>(k), e.cfg.nr, e.cfg.s, e.cfg.persist, e.cfg.bz, e.cfg.split, e.us);
         if (n > 0) off += (size_t)n;
     }
     return (int)off;

@@ -248,6 +248,17 @@ template <int P, int NC, bool NT = false> struct RawRec {
     }
 };
 
+// The values a record holds after a store in precision P (round trip through
+// the storage words in registers), for norms of what was actually written.
+template <int P, int NC, class V>
+__device__ __forceinline__ void round_rec(const V* in, V* out) {
+    using T = Rec<P, NC>;
+#pragma unroll
+    for (int p = 0; p < T::NFULL; ++p) St<P>::unpack16(St<P>::pack16(in + p * T::K), out + p * T::K);
+    if constexpr (T::TAILB == 8) St<P>::unpack8(St<P>::pack8(in + T::NFULL * T::K), out + T::NFULL * T::K);
+    if constexpr (T::TAILB == 4) St<P>::unpack4(St<P>::pack4(in + T::NFULL * T::K), out + T::NFULL * T::K);
+}
+
 template <int P, int NC, class V>
 __device__ __forceinline__ void store_rec(uint8_t* __restrict__ base, uint32_t n, uint32_t i, const V* v) {
     using T = Rec<P, NC>;

@@ -59,9 +59,9 @@ hipError_t launch_hop_single(const HopLaunch& h, hipStream_t s);   // one lane p
 // workgroup (64, 128 or 256), up to 256 / s rhs groups per workgroup and the
 // rest in grid rows; persist = 1: a grid of min(#blocks, 8 * 256) workgroups
 // (a multiple of 8) looping over site blocks.
-struct MrhsCfg { int nr, s, persist, bz; };
+struct MrhsCfg { int nr, s, persist, bz, split; };
 hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t st);
-int set_mrhs_shape(int nr, int sites, int persist, int bz);   // 0 ok, -1 bad value
+int set_mrhs_shape(int nr, int sites, int persist, int bz, int split);   // 0 ok, -1 bad
 int tuning_report(char* buf, size_t len);             // JSON lines, returns length
 
 // ---- BLAS-1 on packed spinor fields (one parity, nrhs fields) -------------

@@ -55,7 +55,7 @@ _SIGS = {
     "wilson_eo_strerror": (C.c_char_p, [C.c_int]),
     "weo_selftest": (C.c_int, []),
     "weo_format_supported": (C.c_int, [_P(weo_format)]),
-    "weo_set_mrhs_shape": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int]),
+    "weo_set_mrhs_shape": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "weo_tuning_report": (C.c_int, [C.c_char_p, C.c_size_t]),
     "weo_gauge_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format)]),
     "weo_spinor_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format), C.c_int]),

@@ -160,3 +160,17 @@ def test_bitwise_repeatable():
     b = lat.apply(u_dev, x_dev, fmt)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_apply_48_3x96_fp64_sampled():
+    """The outer operator of the mixed-precision workload at full size
+    (48^3x96, kappa = 0.1265, eps = 0.7, FP64, 18-real links): the true
+    residual of every defect-correction step is computed with this apply."""
+    dims = (48, 48, 48, 96)
+    print("apply 48^3x96 f64 sampled", flush=True)
+    lat, fmt, u_dev, x_dev, u_or, psi_or = _setup(dims, ("f64", "f64", 18), 301, kappa=0.1265, eps=0.7)
+    out = lat.apply(u_dev, x_dev, fmt)
+    got = lat.unpack_spinor(out, fmt).cpu().numpy().reshape(-1, 4, 3)
+    sites = _sample_sites(dims, 16, 7)
+    want = W.apply_m_at_sites(u_or, psi_or, lat.kappa, np.array(lat.bc), sites)
+    assert np.linalg.norm(got[sites] - want) / np.linalg.norm(want) <= 1e-12

@@ -61,6 +61,24 @@ def test_apply_autograd_matches_oracle(dtype):
     assert rel_err(f, F.link_force_l1(u, psi, eta, kappa, PH)) <= tol
 
 
+def test_fp32_gradients_16_3x32_vs_fp64_oracle():
+    """FP32 autograd at 16^3x32 against the FP64 oracle gradients (no finite
+    differences in FP32): spinor gradient and link gradient within 1e-5."""
+    print("fp32 gradients 16^3x32", flush=True)
+    dims, kappa = (16, 16, 16, 32), 0.125
+    lat = Lattice(dims, kappa, AP)
+    u = cached_gauge(dims, 0.5, 501)
+    psi = inputs.gen_spinor_half(dims, 502)
+    eta = inputs.gen_spinor_half(dims, 503)
+    ut = to_device(u).to(torch.complex64).requires_grad_(True)
+    pt = to_device(psi).to(torch.complex64).requires_grad_(True)
+    et = to_device(eta).to(torch.complex64)
+    loss = (et.conj() * wilson_apply(ut, pt, lat)).real.sum()
+    loss.backward()
+    assert rel_err(pt.grad.cpu().numpy(), F.grad_psi_l1(u, eta, kappa, PH)) <= 1e-5
+    assert rel_err(ut.grad.cpu().numpy(), F.link_grad_l1(u, psi, eta, kappa, PH)) <= 1e-5
+
+
 def test_solve_autograd_matches_oracle_small():
     print("solve autograd 4x4x2x4", flush=True)
     dims, kappa = (4, 4, 2, 4), 0.125

@@ -13,8 +13,8 @@ from tests._helpers import AP, ROUND, link_as_stored, rel_err
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-6, "f16": 2e-3, "bf16": 1e-2}
-SHAPES = [(1, 0, 0, 0)] + [(nr, s, p, bz) for nr in (2, 3, 4, 6) for s in (64, 128, 256)
-                           for p in (0, 1) for bz in (0, 2)]
+SHAPES = [(1, 0, 0, 0, 0)] + [(nr, s, p, bz, sp) for nr in (2, 3, 4, 6) for s in (64, 128, 256)
+                              for p in (0, 1) for bz in (0, 2) for sp in (0, 1)]
 
 
 def _setup(dims, fmt_t, nrhs, seed=700):
@@ -30,7 +30,7 @@ def _setup(dims, fmt_t, nrhs, seed=700):
 @pytest.fixture(autouse=True)
 def _reset_shape():
     yield
-    WE.weo_set_mrhs_shape(0, 0, 0, 0)
+    WE.weo_set_mrhs_shape(0, 0, 0, 0, 0)
 
 
 @pytest.mark.parametrize("fmt_t", [("f32", "f32", 18), ("f64", "f64", 12), ("bf16", "f16", 12)],
@@ -59,7 +59,7 @@ def test_tuned_apply_matches_oracle(nrhs):
     dims = (8, 4, 6, 4)
     print(f"mrhs tuned apply nrhs={nrhs}", flush=True)
     lat, fmt, u_d, x_d, u_o, psi_o = _setup(dims, ("f32", "f32", 12), nrhs, seed=710)
-    WE.weo_set_mrhs_shape(0, 0, 0, 0)
+    WE.weo_set_mrhs_shape(0, 0, 0, 0, 0)
     out = lat.apply(u_d, x_d, fmt, nrhs=nrhs)
     got = lat.unpack_spinor(out, fmt, nrhs=nrhs).cpu().numpy()
     ph = np.array(AP, dtype=np.complex128)
@@ -69,7 +69,8 @@ def test_tuned_apply_matches_oracle(nrhs):
 
 
 def test_bad_shape_rejected():
-    assert WE.weo_set_mrhs_shape(5, 64, 0, 0) == WE.WEO_ERR_ARG
-    assert WE.weo_set_mrhs_shape(2, 96, 0, 0) == WE.WEO_ERR_ARG
-    assert WE.weo_set_mrhs_shape(2, 64, 2, 0) == WE.WEO_ERR_ARG
-    assert WE.weo_set_mrhs_shape(2, 64, 0, -1) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(5, 64, 0, 0, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(2, 96, 0, 0, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(2, 64, 2, 0, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(2, 64, 0, -1, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(2, 64, 0, 0, 2) == WE.WEO_ERR_ARG
