@@ -110,7 +110,10 @@ int weo_format_supported(const weo_format* fmt);
  * times every candidate shape on the first call per (lattice, format,
  * nrhs) -- on the caller's stream and buffers, with one stream
  * synchronisation -- and caches the fastest for the process.  nr = 1: one
- * lane per (site, rhs).  nr in {2, 3, 4, 6} (FP64 uses at most 3) with
+ * lane per (site, rhs).  nr = -1: one lane per site holding its 8 links in
+ * registers while it walks all right-hand sides in turn (FP32/FP16/BF16
+ * spinors; FP64 falls back to nr = 1).  nr in {2, 3, 4, 6} (FP64 uses at
+ * most 3) with
  * sites per workgroup in {64, 128, 256}, persist in {0, 1}, bz in 0..64 and
  * split in {0, 1} forces that shape.  bz > 0 visits the lattice in strips of
  * bz z-planes, all t per strip (ignored where the lattice or workgroup size
@@ -156,6 +159,17 @@ int wilson_eo_hop(const weo_lattice* lat, const weo_format* fmt,
                   int out_parity, int dagger,
                   const void* u, const void* in, void* out,
                   int nrhs, void* stream);
+
+/* Hop with an axpy epilogue: out = y + alpha * P_{out_parity} H P_{1-out_parity} in
+ * (H^dag with dagger = 1).  With D_ee = D_oo = 1 this gives the steps either
+ * side of the even-odd solve of Eqs. (4)-(5):
+ *   right-hand side of Eq. (4):  b_e  = eta_e + kappa H_eo eta_o   (out_parity 0)
+ *   Eq. (5):                     xi_o = eta_o + kappa H_oe xi_e    (out_parity 1)
+ * y (parity out_parity) may be the same buffer as out; in must not overlap out. */
+int wilson_eo_hop_axpy(const weo_lattice* lat, const weo_format* fmt,
+                       int out_parity, int dagger, double alpha,
+                       const void* u, const void* in, const void* y, void* out,
+                       int nrhs, void* stream);
 
 /* The even-odd operator of Eq. (4), left-hand side, on the even sublattice:
  *   out = M in = in - kappa^2 H_eo H_oe in   (dagger = 0)

@@ -215,6 +215,41 @@ int wilson_eo_hop(const weo_lattice* lat, const weo_format* fmt, int out_parity,
     return hip_status(launch_hop(h, static_cast<hipStream_t>(stream)));
 }
 
+int wilson_eo_hop_axpy(const weo_lattice* lat, const weo_format* fmt, int out_parity, int dagger,
+                       double alpha, const void* u, const void* in, const void* y, void* out, int nrhs,
+                       void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if ((out_parity != 0 && out_parity != 1) || (dagger != 0 && dagger != 1)) return WEO_ERR_ARG;
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS || !std::isfinite(alpha)) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(u));
+    WEO_TRY(check_ptr(in));
+    WEO_TRY(check_ptr(y));
+    WEO_TRY(check_ptr(out));
+    const size_t sb = (size_t)nrhs * spinor_field_bytes(g, id);
+    // each lane reads its own y record before writing the same out record,
+    // so y == out is safe; partial overlap is not
+    if (overlaps(in, sb, out, sb) || overlaps(u, gauge_field_bytes(g, id), out, sb) ||
+        (y != out && overlaps(y, sb, out, sb)))
+        return WEO_ERR_ARG;
+    HopLaunch h;
+    h.g = g;
+    h.fmt = id;
+    h.out_par = out_parity;
+    h.dagger = dagger;
+    phases_of(lat, h.phase);
+    h.u = u;
+    h.in = in;
+    h.out = out;
+    h.y = y;
+    h.alpha = alpha;
+    h.partial = nullptr;
+    h.nrhs = nrhs;
+    return hip_status(launch_hop(h, static_cast<hipStream_t>(stream)));
+}
+
 int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger, const void* u,
                     const void* in, void* out, void* tmp, int nrhs, void* stream) {
     Geom g;

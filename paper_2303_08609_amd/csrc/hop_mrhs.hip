@@ -197,6 +197,132 @@ __global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
     }
 }
 
+// ---- link-resident form -------------------------------------------------------
+// One lane per site keeps the raw words of its 8 links in registers and
+// walks the right-hand sides one after the other, so every link is read once
+// per launch while each wavefront touches one spinor field at a time (the
+// neighbour records stay in L2 as for a single right-hand side).  Built for
+// FP32, FP16 and BF16 spinors (FP64 links would not fit the register file).
+template <class RR> __device__ __forceinline__ void lr_pin(RR& r) {
+    constexpr int NW = sizeof(r.w) / sizeof(uint4);
+#pragma unroll
+    for (int p = 0; p < NW; ++p) asm volatile("" : "+v"(r.w[p].x), "+v"(r.w[p].y), "+v"(r.w[p].z), "+v"(r.w[p].w));
+    asm volatile("" : "+v"(r.t8.x), "+v"(r.t8.y), "+v"(r.t4));
+}
+
+template <int SP, int LP, bool L12, bool DAG, bool CPH, int K, class C>
+__device__ __forceinline__ void lr_consume(const HopParams& P, const Nbr& nb,
+                                           const RawRec<LP, L12 ? 6 : 9, hop_nt<SP>()>& ln,
+                                           const RawRec<SP, 12>& sp, C* acc) {
+    constexpr int MU = K / 2;
+    constexpr int SF = DAG ? -1 : 1;
+    using R = decltype(C().x);
+    C p[12], u[9];
+    sp.unpack(p);
+    {
+        cx<typename St<LP>::real> w[9];
+        ln.unpack(w);
+#pragma unroll
+        for (int k = 0; k < (L12 ? 6 : 9); ++k) { u[k].x = (R)w[k].x; u[k].y = (R)w[k].y; }
+        if constexpr (L12) {
+            u[6] = conj_(sub(mul(u[1], u[5]), mul(u[2], u[4])));
+            u[7] = conj_(sub(mul(u[2], u[3]), mul(u[0], u[5])));
+            u[8] = conj_(sub(mul(u[0], u[4]), mul(u[1], u[3])));
+        }
+    }
+    C phase;
+    phase.x = (R)P.ph[MU][0];
+    phase.y = (R)P.ph[MU][1];
+    if constexpr ((K & 1) == 0) hop_dir<MU, SF, true, CPH>(p, u, nb.edge[K], phase, acc);
+    else hop_dir<MU, -SF, false, CPH>(p, u, nb.edge[K], conj_(phase), acc);
+}
+
+template <int SP, int LP, bool L12, bool DAG, bool CPH, int D, int K, class C>
+__device__ __forceinline__ void lr_step(const HopParams& P, const uint8_t* in, const Nbr& nb,
+                                        const RawRec<LP, L12 ? 6 : 9, hop_nt<SP>()> (&lk)[8],
+                                        RawRec<SP, 12> (&ring)[D + 1], C* acc) {
+    if constexpr (K + D < 8) ring[(K + D) % (D + 1)].load(in, P.g.vh, nb.i[K + D]);
+    __builtin_amdgcn_sched_barrier(0);
+    lr_consume<SP, LP, L12, DAG, CPH, K>(P, nb, lk[K], ring[K % (D + 1)], acc);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (K + 1 < 8) lr_step<SP, LP, L12, DAG, CPH, D, K + 1>(P, in, nb, lk, ring, acc);
+}
+
+template <int SP, int LP, bool L12, bool DAG, bool CPH>
+__global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
+    using R = typename Arith<SP>::R;
+    using C = cx<R>;
+    constexpr int D = 1;
+    const HopParams& P = M.h;
+    const uint32_t S = blockDim.x;
+    const uint32_t n = P.g.vh;
+    const uint32_t nchunk = (n + 63) >> 6;
+    for (uint32_t b = blockIdx.x; b < M.nblk; b += gridDim.x) {
+        const uint32_t blk = xcd_block(b, M.nblk, P.remap);
+        const uint32_t base = block_first_site(P.sched, P.g, blk, S);
+        const uint32_t ih = base + threadIdx.x;
+        const bool valid = ih < n;
+        Nbr nb;
+        RawRec<LP, L12 ? 6 : 9, hop_nt<SP>()> lk[8];
+        if (valid) {
+            const Site s = decode(P.g, ih, P.out_par);
+            nb = neighbours(P.g, s);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int mu = k >> 1;
+                const bool fwd = (k & 1) == 0;
+                lk[k].load(P.u + (size_t)(2 * mu + (fwd ? P.out_par : 1 - P.out_par)) * P.link_block, n,
+                           fwd ? ih : nb.i[k]);
+            }
+        }
+        for (int r = 0; r < M.nrhs; ++r) {
+            double nrm = 0.0;
+            if (valid) {
+                // keep the links as raw words across the loop: without this the
+                // compiler hoists their conversion out of it and spills
+#pragma unroll
+                for (int k = 0; k < 8; ++k) lr_pin(lk[k]);
+                const uint8_t* in = P.in + (size_t)r * P.spinor_bytes;
+                C acc[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = czero<C>();
+                RawRec<SP, 12> ring[D + 1];
+#pragma unroll
+                for (int k = 0; k < D; ++k) ring[k].load(in, n, nb.i[k]);
+                lr_step<SP, LP, L12, DAG, CPH, D, 0>(P, in, nb, lk, ring, acc);
+                if (P.y) {
+                    C yv[12];
+                    load_rec<SP, 12>(P.y + (size_t)r * P.spinor_bytes, n, ih, yv);
+                    const R a = (R)P.alpha;
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        acc[k].x = fma(a, acc[k].x, yv[k].x);
+                        acc[k].y = fma(a, acc[k].y, yv[k].y);
+                    }
+                }
+                store_rec<SP, 12>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
+                if (P.partial) {
+                    C st[12];
+                    if constexpr (SP == P_F32) {
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) st[k] = acc[k];
+                    } else {
+                        round_rec<SP, 12>(acc, st);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        nrm += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
+                }
+            }
+            if (P.partial) {
+                const double t = wave_sum64(nrm);
+                const uint32_t chunk = (base + (threadIdx.x & ~63u)) >> 6;
+                if ((threadIdx.x & 63) == 0 && chunk < nchunk) P.partial[(size_t)r * nchunk + chunk] = t;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host ----
 static HopParams hop_params(const HopLaunch& h) {
     HopParams P;
@@ -242,10 +368,48 @@ static hipError_t mrhs_fmt(const HopLaunch& h, const MrhsParams& M, int nr, dim3
     return hipErrorInvalidValue;
 }
 
+template <int SP, int LP, bool L12>
+static hipError_t lr_fmt(const HopLaunch& h, const MrhsParams& M, dim3 grid, dim3 block, hipStream_t s) {
+    bool cph = false;
+    for (int m = 0; m < 4; ++m) cph = cph || h.phase[m][1] != 0.0;
+#define WEO_LR(D, CP) hipLaunchKernelGGL((k_hop_lr<SP, LP, L12, D, CP>), grid, block, 0, s, M)
+    if (h.dagger) { if (cph) WEO_LR(true, true); else WEO_LR(true, false); }
+    else { if (cph) WEO_LR(false, true); else WEO_LR(false, false); }
+#undef WEO_LR
+    return hipGetLastError();
+}
+
+static hipError_t launch_hop_lr(const HopLaunch& h, const MrhsParams& M, dim3 grid, dim3 block,
+                                hipStream_t s) {
+    switch (h.fmt) {
+        case FMT_S_S_18: return lr_fmt<P_F32, P_F32, false>(h, M, grid, block, s);
+        case FMT_S_S_12: return lr_fmt<P_F32, P_F32, true>(h, M, grid, block, s);
+        case FMT_H_H_18: return lr_fmt<P_F16, P_F16, false>(h, M, grid, block, s);
+        case FMT_H_H_12: return lr_fmt<P_F16, P_F16, true>(h, M, grid, block, s);
+        case FMT_B_H_18: return lr_fmt<P_BF16, P_F16, false>(h, M, grid, block, s);
+        case FMT_B_H_12: return lr_fmt<P_BF16, P_F16, true>(h, M, grid, block, s);
+        default: return hipErrorInvalidValue;       // FP64: not built (register file)
+    }
+}
+
+bool lr_supported(int fmt) { return fmt_info(fmt).spinor_prec != P_F64; }
+
 hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) {
     MrhsParams M;
     M.h = hop_params(h);
     M.h.sched = make_sched(h.g, c.bz, (uint32_t)c.s);
+    if (c.nr < 0) {
+        // link-resident: one lane per site, all rhs in turn
+        M.nrhs = h.nrhs;
+        M.nblk = (h.g.vh + (uint32_t)c.s - 1) / (uint32_t)c.s;
+        uint32_t nwg = M.nblk;
+        if (c.persist) {
+            const uint32_t cap = 8u * 256u;
+            if (nwg > cap) nwg = cap;
+            nwg = ((nwg + 7u) / 8u) * 8u;
+        }
+        return launch_hop_lr(h, M, dim3(nwg), dim3((unsigned)c.s), s);
+    }
     M.nrhs = h.nrhs;
     M.nblk = (h.g.vh + (uint32_t)c.s - 1) / (uint32_t)c.s;
     const int groups = (h.nrhs + c.nr - 1) / c.nr;
@@ -288,6 +452,13 @@ std::vector<MrhsCfg> candidates(const HopLaunch& h) {
     std::vector<MrhsCfg> v;
     v.push_back({1, 0, 0, 0, 0});
     const bool wide = fmt_info(h.fmt).spinor_prec == P_F64;
+    if (lr_supported(h.fmt))
+        for (int s : {64, 128, 256})
+            for (int persist : {0, 1})
+                for (int bz : {0, 2, 4, 8}) {
+                    if (bz && make_sched(h.g, bz, (uint32_t)s).bz != bz) continue;
+                    v.push_back({-1, s, persist, bz, 0});
+                }
     const int nrs[] = {2, 3, 4, 6};
     for (int nr : nrs) {
         if (nr > h.nrhs || (wide && nr > 3)) continue;
@@ -355,7 +526,16 @@ int set_mrhs_shape(int nr, int sites, int persist, int bz, int split) {
         g_forced = {nr, 0, 0, 0, 0};
         return 0;
     }
+    if (nr < -1) return -1;
     if (split != 0 && split != 1) return -1;
+    if (nr == -1) {
+        if (sites != 64 && sites != 128 && sites != 256) return -1;
+        if (persist != 0 && persist != 1) return -1;
+        if (bz < 0 || bz > 64) return -1;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_forced = {-1, sites, persist, bz, 0};
+        return 0;
+    }
     if (nr != 2 && nr != 3 && nr != 4 && nr != 6) return -1;
     if (sites != 64 && sites != 128 && sites != 256) return -1;
     if (persist != 0 && persist != 1) return -1;
@@ -373,6 +553,10 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
         forced = g_forced;
     }
     if (forced.nr == 1) return launch_hop_single(h, s);
+    if (forced.nr == -1) {
+        if (!lr_supported(h.fmt)) return launch_hop_single(h, s);
+        return launch_hop_mrhs(h, forced, s);
+    }
     if (forced.nr > 1) {
         MrhsCfg c = forced;
         const bool wide = fmt_info(h.fmt).spinor_prec == P_F64;

@@ -122,6 +122,14 @@ class Lattice:
                                 _ptr(x), _ptr(out), int(nrhs), _stream()), "wilson_eo_hop")
         return out
 
+    def hop_axpy(self, u, x, y, fmt: Format, out_parity, alpha, dagger=False, nrhs=1, out=None):
+        """out = y + alpha * P_p H P_{1-p} x (out may be y)."""
+        out = self.new_spinor(fmt, nrhs) if out is None else out
+        W.check(W.wilson_eo_hop_axpy(self.c, fmt.c, int(out_parity), int(bool(dagger)), float(alpha),
+                                     _ptr(u), _ptr(x), _ptr(y), _ptr(out), int(nrhs), _stream()),
+                "wilson_eo_hop_axpy")
+        return out
+
     def apply(self, u, x, fmt: Format, dagger=False, nrhs=1, out=None, tmp=None):
         out = self.new_spinor(fmt, nrhs) if out is None else out
         tmp = self.new_spinor(fmt, nrhs) if tmp is None else tmp

@@ -66,6 +66,8 @@ _SIGS = {
                                     _vp, C.c_int, _vp]),
     "wilson_eo_hop": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int, _vp, _vp,
                                 _vp, C.c_int, _vp]),
+    "wilson_eo_hop_axpy": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int, C.c_double,
+                                     _vp, _vp, _vp, _vp, C.c_int, _vp]),
     "wilson_eo_apply": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, _vp, _vp, _vp,
                                   _vp, C.c_int, _vp]),
     "wilson_eo_cg_workspace_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format),
@@ -139,6 +141,7 @@ weo_pack_gauge = _call("weo_pack_gauge")
 weo_pack_spinor = _call("weo_pack_spinor")
 weo_unpack_spinor = _call("weo_unpack_spinor")
 wilson_eo_hop = _call("wilson_eo_hop")
+wilson_eo_hop_axpy = _call("wilson_eo_hop_axpy")
 wilson_eo_apply = _call("wilson_eo_apply")
 wilson_eo_cg_workspace_bytes = _call("wilson_eo_cg_workspace_bytes")
 wilson_eo_cg = _call("wilson_eo_cg")
