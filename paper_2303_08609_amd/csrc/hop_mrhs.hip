@@ -237,22 +237,27 @@ __device__ __forceinline__ void lr_consume(const HopParams& P, const Nbr& nb,
     else hop_dir<MU, -SF, false, CPH>(p, u, nb.edge[K], conj_(phase), acc);
 }
 
+// Neighbour records flow through a ring of D+1 slots (D+1 divides 8, so a
+// direction always lands in the same slot); the last D directions of one
+// right-hand side prefetch the first D records of the next.
 template <int SP, int LP, bool L12, bool DAG, bool CPH, int D, int K, class C>
-__device__ __forceinline__ void lr_step(const HopParams& P, const uint8_t* in, const Nbr& nb,
+__device__ __forceinline__ void lr_step(const HopParams& P, const uint8_t* in, const uint8_t* in_next,
+                                        const Nbr& nb,
                                         const RawRec<LP, L12 ? 6 : 9, hop_nt<SP>()> (&lk)[8],
                                         RawRec<SP, 12> (&ring)[D + 1], C* acc) {
     if constexpr (K + D < 8) ring[(K + D) % (D + 1)].load(in, P.g.vh, nb.i[K + D]);
+    else ring[(K + D) % (D + 1)].load(in_next, P.g.vh, nb.i[K + D - 8]);
     __builtin_amdgcn_sched_barrier(0);
     lr_consume<SP, LP, L12, DAG, CPH, K>(P, nb, lk[K], ring[K % (D + 1)], acc);
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (K + 1 < 8) lr_step<SP, LP, L12, DAG, CPH, D, K + 1>(P, in, nb, lk, ring, acc);
+    if constexpr (K + 1 < 8) lr_step<SP, LP, L12, DAG, CPH, D, K + 1>(P, in, in_next, nb, lk, ring, acc);
 }
 
-template <int SP, int LP, bool L12, bool DAG, bool CPH>
+template <int SP, int LP, bool L12, bool DAG, bool CPH, int D>
 __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
+    static_assert(8 % (D + 1) == 0, "ring size must divide the 8 directions");
     using R = typename Arith<SP>::R;
     using C = cx<R>;
-    constexpr int D = 1;
     const HopParams& P = M.h;
     const uint32_t S = blockDim.x;
     const uint32_t n = P.g.vh;
@@ -264,6 +269,7 @@ __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
         const bool valid = ih < n;
         Nbr nb;
         RawRec<LP, L12 ? 6 : 9, hop_nt<SP>()> lk[8];
+        RawRec<SP, 12> ring[D + 1];
         if (valid) {
             const Site s = decode(P.g, ih, P.out_par);
             nb = neighbours(P.g, s);
@@ -274,6 +280,8 @@ __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
                 lk[k].load(P.u + (size_t)(2 * mu + (fwd ? P.out_par : 1 - P.out_par)) * P.link_block, n,
                            fwd ? ih : nb.i[k]);
             }
+#pragma unroll
+            for (int k = 0; k < D; ++k) ring[k].load(P.in, n, nb.i[k]);
         }
         for (int r = 0; r < M.nrhs; ++r) {
             double nrm = 0.0;
@@ -283,13 +291,13 @@ __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
 #pragma unroll
                 for (int k = 0; k < 8; ++k) lr_pin(lk[k]);
                 const uint8_t* in = P.in + (size_t)r * P.spinor_bytes;
+                // after the last right-hand side the prefetch re-reads this one
+                // (cache hits, no branch inside the unrolled directions)
+                const uint8_t* in_next = r + 1 < M.nrhs ? in + P.spinor_bytes : in;
                 C acc[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) acc[k] = czero<C>();
-                RawRec<SP, 12> ring[D + 1];
-#pragma unroll
-                for (int k = 0; k < D; ++k) ring[k].load(in, n, nb.i[k]);
-                lr_step<SP, LP, L12, DAG, CPH, D, 0>(P, in, nb, lk, ring, acc);
+                lr_step<SP, LP, L12, DAG, CPH, D, 0>(P, in, in_next, nb, lk, ring, acc);
                 if (P.y) {
                     C yv[12];
                     load_rec<SP, 12>(P.y + (size_t)r * P.spinor_bytes, n, ih, yv);
@@ -368,26 +376,33 @@ static hipError_t mrhs_fmt(const HopLaunch& h, const MrhsParams& M, int nr, dim3
     return hipErrorInvalidValue;
 }
 
-template <int SP, int LP, bool L12>
-static hipError_t lr_fmt(const HopLaunch& h, const MrhsParams& M, dim3 grid, dim3 block, hipStream_t s) {
+template <int SP, int LP, bool L12, int D>
+static hipError_t lr_depth(const HopLaunch& h, const MrhsParams& M, dim3 grid, dim3 block, hipStream_t s) {
     bool cph = false;
     for (int m = 0; m < 4; ++m) cph = cph || h.phase[m][1] != 0.0;
-#define WEO_LR(D, CP) hipLaunchKernelGGL((k_hop_lr<SP, LP, L12, D, CP>), grid, block, 0, s, M)
+#define WEO_LR(DG, CP) hipLaunchKernelGGL((k_hop_lr<SP, LP, L12, DG, CP, D>), grid, block, 0, s, M)
     if (h.dagger) { if (cph) WEO_LR(true, true); else WEO_LR(true, false); }
     else { if (cph) WEO_LR(false, true); else WEO_LR(false, false); }
 #undef WEO_LR
     return hipGetLastError();
 }
 
-static hipError_t launch_hop_lr(const HopLaunch& h, const MrhsParams& M, dim3 grid, dim3 block,
+template <int SP, int LP, bool L12>
+static hipError_t lr_fmt(const HopLaunch& h, const MrhsParams& M, int depth, dim3 grid, dim3 block,
+                         hipStream_t s) {
+    return depth == 3 ? lr_depth<SP, LP, L12, 3>(h, M, grid, block, s)
+                      : lr_depth<SP, LP, L12, 1>(h, M, grid, block, s);
+}
+
+static hipError_t launch_hop_lr(const HopLaunch& h, const MrhsParams& M, int depth, dim3 grid, dim3 block,
                                 hipStream_t s) {
     switch (h.fmt) {
-        case FMT_S_S_18: return lr_fmt<P_F32, P_F32, false>(h, M, grid, block, s);
-        case FMT_S_S_12: return lr_fmt<P_F32, P_F32, true>(h, M, grid, block, s);
-        case FMT_H_H_18: return lr_fmt<P_F16, P_F16, false>(h, M, grid, block, s);
-        case FMT_H_H_12: return lr_fmt<P_F16, P_F16, true>(h, M, grid, block, s);
-        case FMT_B_H_18: return lr_fmt<P_BF16, P_F16, false>(h, M, grid, block, s);
-        case FMT_B_H_12: return lr_fmt<P_BF16, P_F16, true>(h, M, grid, block, s);
+        case FMT_S_S_18: return lr_fmt<P_F32, P_F32, false>(h, M, depth, grid, block, s);
+        case FMT_S_S_12: return lr_fmt<P_F32, P_F32, true>(h, M, depth, grid, block, s);
+        case FMT_H_H_18: return lr_fmt<P_F16, P_F16, false>(h, M, depth, grid, block, s);
+        case FMT_H_H_12: return lr_fmt<P_F16, P_F16, true>(h, M, depth, grid, block, s);
+        case FMT_B_H_18: return lr_fmt<P_BF16, P_F16, false>(h, M, depth, grid, block, s);
+        case FMT_B_H_12: return lr_fmt<P_BF16, P_F16, true>(h, M, depth, grid, block, s);
         default: return hipErrorInvalidValue;       // FP64: not built (register file)
     }
 }
@@ -399,7 +414,7 @@ hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) 
     M.h = hop_params(h);
     M.h.sched = make_sched(h.g, c.bz, (uint32_t)c.s);
     if (c.nr < 0) {
-        // link-resident: one lane per site, all rhs in turn
+        // link-resident: one lane per site, all rhs in turn; -nr is the ring depth
         M.nrhs = h.nrhs;
         M.nblk = (h.g.vh + (uint32_t)c.s - 1) / (uint32_t)c.s;
         uint32_t nwg = M.nblk;
@@ -408,7 +423,7 @@ hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) 
             if (nwg > cap) nwg = cap;
             nwg = ((nwg + 7u) / 8u) * 8u;
         }
-        return launch_hop_lr(h, M, dim3(nwg), dim3((unsigned)c.s), s);
+        return launch_hop_lr(h, M, -c.nr, dim3(nwg), dim3((unsigned)c.s), s);
     }
     M.nrhs = h.nrhs;
     M.nblk = (h.g.vh + (uint32_t)c.s - 1) / (uint32_t)c.s;
@@ -457,7 +472,7 @@ std::vector<MrhsCfg> candidates(const HopLaunch& h) {
             for (int persist : {0, 1})
                 for (int bz : {0, 2, 4, 8}) {
                     if (bz && make_sched(h.g, bz, (uint32_t)s).bz != bz) continue;
-                    v.push_back({-1, s, persist, bz, 0});
+                    for (int nr : {-1, -3}) v.push_back({nr, s, persist, bz, 0});
                 }
     const int nrs[] = {2, 3, 4, 6};
     for (int nr : nrs) {
@@ -526,14 +541,14 @@ int set_mrhs_shape(int nr, int sites, int persist, int bz, int split) {
         g_forced = {nr, 0, 0, 0, 0};
         return 0;
     }
-    if (nr < -1) return -1;
+    if (nr < -3 || nr == -2) return -1;
     if (split != 0 && split != 1) return -1;
-    if (nr == -1) {
+    if (nr == -1 || nr == -3) {
         if (sites != 64 && sites != 128 && sites != 256) return -1;
         if (persist != 0 && persist != 1) return -1;
         if (bz < 0 || bz > 64) return -1;
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_forced = {-1, sites, persist, bz, 0};
+        g_forced = {nr, sites, persist, bz, 0};
         return 0;
     }
     if (nr != 2 && nr != 3 && nr != 4 && nr != 6) return -1;
@@ -553,7 +568,7 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
         forced = g_forced;
     }
     if (forced.nr == 1) return launch_hop_single(h, s);
-    if (forced.nr == -1) {
+    if (forced.nr < 0) {
         if (!lr_supported(h.fmt)) return launch_hop_single(h, s);
         return launch_hop_mrhs(h, forced, s);
     }

@@ -13,7 +13,7 @@ from tests._helpers import AP, ROUND, link_as_stored, rel_err
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-6, "f16": 2e-3, "bf16": 1e-2}
-SHAPES = [(1, 0, 0, 0, 0)] + [(-1, s, p, bz, 0) for s in (64, 128, 256) for p in (0, 1)
+SHAPES = [(1, 0, 0, 0, 0)] + [(d, s, p, bz, 0) for d in (-1, -3) for s in (64, 128, 256) for p in (0, 1)
                               for bz in (0, 2)] + [(nr, s, p, bz, sp) for nr in (2, 3, 4, 6) for s in (64, 128, 256)
                               for p in (0, 1) for bz in (0, 2) for sp in (0, 1)]
 
