@@ -68,6 +68,12 @@ _SIGS = {
                                 _vp, C.c_int, _vp]),
     "wilson_eo_hop_axpy": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int, C.c_double,
                                      _vp, _vp, _vp, _vp, C.c_int, _vp]),
+    "weo_face_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format), C.c_int]),
+    "wilson_eo_face_pack": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int, _vp, _vp,
+                                      _vp, _vp, C.c_int, _vp]),
+    "wilson_eo_face_unpack": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int,
+                                        _P(C.c_double), _P(C.c_double), C.c_double, _vp, _vp, _vp,
+                                        _vp, C.c_int, _vp]),
     "wilson_eo_apply": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, _vp, _vp, _vp,
                                   _vp, C.c_int, _vp]),
     "wilson_eo_cg_workspace_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format),
@@ -143,6 +149,9 @@ weo_unpack_spinor = _call("weo_unpack_spinor")
 wilson_eo_hop = _call("wilson_eo_hop")
 wilson_eo_hop_axpy = _call("wilson_eo_hop_axpy")
 wilson_eo_apply = _call("wilson_eo_apply")
+weo_face_bytes = _call("weo_face_bytes")
+wilson_eo_face_pack = _call("wilson_eo_face_pack")
+wilson_eo_face_unpack = _call("wilson_eo_face_unpack")
 wilson_eo_cg_workspace_bytes = _call("wilson_eo_cg_workspace_bytes")
 wilson_eo_cg = _call("wilson_eo_cg")
 wilson_eo_force = _call("wilson_eo_force")
