@@ -13,6 +13,10 @@ The JSON line also carries:
   cpu_baseline  the FP64 NumPy oracle timed on a sample of the same workload
                 on this host (single thread);
   variants      the same apply in other storage formats;
+  t_split_32x32x32x8
+                one device's share of 32^3x64 cut along t into 8 slabs: the
+                slab hop as bulk kernel + face pack + face unpack (faces
+                exchanged with itself) against the slab's periodic hop;
   solve         solve times to a true FP64 residual of 1e-10 (and FP32 CGLS to
                 1e-6): FP64 defect correction with FP16/BF16 inner solves
                 against FP32 inner solves, for one source at 32^3x64, twelve
@@ -229,6 +233,43 @@ def main():
         }
         print(f"[bench] {vs}: {variants[vs]}", file=sys.stderr, flush=True)
 
+    # one device's share of a t-split 32^3x64 lattice over 8 devices: the
+    # 32^3x8 slab hop as bulk (zero t phase) + face pack + face unpack,
+    # against the same slab's periodic hop
+    split = {}
+    sdims = (32, 32, 32, 8)
+    slat = Lattice(sdims, KAPPA, (1, 1, 1, -1))
+    sopen = slat.open_t()
+    su = to_device(inputs.gen_gauge(sdims, EPS, SEED_GAUGE))
+    spsi = to_device(inputs.gen_spinor_half(sdims, SEED_SRC))
+    for vs in ("f32/f32/18", "f16/f16/12"):
+        f2 = Format(*parse_fmt(vs))
+        ud = slat.pack_gauge(su, f2)
+        xd = slat.pack_spinor(spsi, f2)
+        out = slat.new_spinor(f2)
+        lo, hi = slat.face_pack(ud, xd, f2, 1)
+        n = max(a.steps // 4, 1)
+        plain = lambda: slat.hop(ud, xd, f2, 1, out=out)
+        bulk = lambda: sopen.hop(ud, xd, f2, 1, out=out)
+        pack = lambda: slat.face_pack(ud, xd, f2, 1, lo=lo, hi=hi)
+        unpack = lambda: slat.face_unpack(ud, hi, lo, out, f2, 1, phase_lo=-1.0, phase_hi=-1.0)
+
+        def whole():
+            pack()
+            bulk()
+            unpack()
+        r = {}
+        for name, fn in (("periodic_hop_us", plain), ("bulk_hop_us", bulk), ("face_pack_us", pack),
+                         ("face_unpack_us", unpack), ("pack_bulk_unpack_us", whole)):
+            for _ in range(a.warmup):
+                fn()
+            r[name] = round(time_loop(fn, n) * 1e3, 2)
+        r["face_bytes_each"] = slat.face_bytes(f2)
+        split[vs] = r
+        print(f"[bench] t-split 32^3x8 {vs}: {r}", file=sys.stderr, flush=True)
+        del ud, xd, out, lo, hi
+    del su, spsi
+
     solve = None
     if not a.no_solve:
         from paper_2303_08609_amd import solve as S
@@ -269,6 +310,7 @@ def main():
                      "hop_us": round(ms_hop * 1e3, 2),
                      "bytes_per_launch": hop_bytes},
         "variants": variants,
+        "t_split_32x32x32x8": split,
     }
     if solve is not None:
         line["solve"] = solve

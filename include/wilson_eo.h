@@ -225,9 +225,14 @@ int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger,
 /* ---- solvers (the paper names none; Sec. 2 says solves dominate) -------- */
 #define WEO_OP_M      0   /* solve M x = b by CGLS (CG on the normal equations) */
 #define WEO_OP_MDAGM  1   /* solve M^dag M x = b by CG */
+#define WEO_OP_DW     2   /* solve D_W x = b of Eq. (2) on the full lattice by CGLS,
+                             without even-odd preconditioning (Sec. 2 compares
+                             the two systems' condition); b and x hold nrhs
+                             full fields, each the packed even half followed by
+                             the packed odd half (2 weo_spinor_bytes(.., 1)) */
 
 typedef struct {
-    int        op;          /* WEO_OP_M or WEO_OP_MDAGM */
+    int        op;          /* WEO_OP_M, WEO_OP_MDAGM or WEO_OP_DW */
     int        nrhs;        /* 1..WEO_MAX_RHS right-hand sides solved together */
     double     tol;         /* target true relative residual ||b - A x|| / ||b|| */
     int        maxiter;     /* cap on inner iterations (per solve) */
@@ -245,7 +250,7 @@ typedef struct {
     int    status;                          /* WEO_OK, WEO_NOT_CONVERGED, WEO_BREAKDOWN */
     int    iters;                           /* inner iterations performed */
     int    outer_iters;                     /* defect-correction steps (mixed) */
-    int    applies;                         /* M or M^dag applications issued */
+    int    applies;                         /* operator (M, M^dag, D_W, D_W^dag) applications */
     double true_rel_resid[WEO_MAX_RHS];     /* recomputed at exit, FP64 for mixed */
     double seconds;                         /* wall time inside the call */
 } weo_solver_info;
@@ -254,7 +259,8 @@ typedef struct {
 size_t wilson_eo_cg_workspace_bytes(const weo_lattice* lat, const weo_format* fmt,
                                     const weo_solver_params* p);
 
-/* Solve for nrhs right-hand sides b (packed, format fmt, even parity) into x.
+/* Solve for nrhs right-hand sides b (packed, format fmt, even parity; full
+ * fields for WEO_OP_DW) into x.
  * u holds the links in format fmt; u_inner the links in p->inner (mixed only,
  * else ignored).  Synchronises `stream` before returning. */
 int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt,

@@ -43,7 +43,7 @@ struct FaceParams {
 template <int S> __device__ __forceinline__ constexpr int t_rows() { return S > 0 ? 6 : 0; }
 
 template <int SP, int LP, bool L12, bool DAG>
-__global__ void __launch_bounds__(256) k_face_pack(const FaceParams P) {
+__global__ void __launch_bounds__(64) k_face_pack(const FaceParams P) {
     using R = typename Arith<SP>::R;
     using C = cx<R>;
     constexpr int SF = DAG ? -1 : 1;
@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) k_face_pack(const FaceParams P) {
 }
 
 template <int SP, int LP, bool L12, bool DAG>
-__global__ void __launch_bounds__(256) k_face_unpack(const FaceParams P) {
+__global__ void __launch_bounds__(64) k_face_unpack(const FaceParams P) {
     using R = typename Arith<SP>::R;
     using C = cx<R>;
     constexpr int SF = DAG ? -1 : 1;
@@ -161,7 +161,8 @@ static FaceParams face_params(const Geom& g, int fmt, int out_par) {
 
 template <int SP, int LP, bool L12>
 static hipError_t face_fmt(bool unpack, int dagger, const FaceParams& P, int nrhs, hipStream_t s) {
-    const dim3 block(256), grid((P.nf + 255) / 256, nrhs, 2);
+    // small grids: 64-lane workgroups spread a face over more compute units
+    const dim3 block(64), grid((P.nf + 63) / 64, nrhs, 2);
     if (unpack) {
         if (dagger) hipLaunchKernelGGL((k_face_unpack<SP, LP, L12, true>), grid, block, 0, s, P);
         else hipLaunchKernelGGL((k_face_unpack<SP, LP, L12, false>), grid, block, 0, s, P);

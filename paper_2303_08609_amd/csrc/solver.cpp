@@ -8,6 +8,9 @@
 //     s = b - M x;  r = M^dag s;  p = r;  gamma = <r, r>
 //     repeat: q = M p;  alpha = gamma / ||q||^2;  x += alpha p;  s -= alpha q;
 //             r = M^dag s;  beta = <r, r> / gamma;  gamma = <r, r>;  p = r + beta p
+//  The same CGLS on the unpreconditioned D_W = 1 - kappa H of Eq. (1) over
+//  both parities (op WEO_OP_DW; a field is its even half followed by its odd
+//  half), for comparing iteration counts with the even-odd system.
 //  CG for M^dag M x = b:
 //     r = b - A x;  p = r;  gamma = <r, r>
 //     repeat: t = M p;  q = M^dag t;  alpha = gamma / ||t||^2;  x += alpha p;
@@ -123,7 +126,10 @@ Workspace carve_ws(const Geom& g, int fmt, const weo_solver_params* p, int inner
 
 struct Ctx {
     const weo_lattice* lat;
-    Geom g;
+    Geom g;                 // the lattice (hop geometry)
+    Geom gb;                // vector geometry: g, or twice the sites for full fields
+    bool full;              // operator on full (both-parity) fields
+    uint32_t nb_apply;      // norm partials per rhs written by an operator apply
     double ph[4][2];
     hipStream_t st;
     int applies;
@@ -157,11 +163,49 @@ hipError_t apply_m(Ctx& c, int fmt, const void* u, int dagger, const void* in, v
     return launch_hop(h, c.st);
 }
 
+// out = D_W in (dagger 0) or D_W^dag in (dagger 1) on full fields [even | odd]:
+//   out_e = in_e - kappa H_eo in_o,   out_o = in_o - kappa H_oe in_e
+// partial = ||out||^2 over both halves.
+hipError_t apply_dw(Ctx& c, int fmt, const void* u, int dagger, const void* in, void* out, int nrhs,
+                    double* partial) {
+    const size_t half = spinor_field_bytes(c.g, fmt);
+    HopLaunch h;
+    h.g = c.g;
+    h.fmt = fmt;
+    h.dagger = dagger;
+    std::memcpy(h.phase, c.ph, sizeof(h.phase));
+    h.u = u;
+    h.nrhs = 1;
+    h.alpha = -c.lat->kappa;
+    h.partial = nullptr;
+    for (int r = 0; r < nrhs; ++r) {
+        const uint8_t* ie = static_cast<const uint8_t*>(in) + (size_t)r * 2 * half;
+        uint8_t* oe = static_cast<uint8_t*>(out) + (size_t)r * 2 * half;
+        for (int par = 0; par < 2; ++par) {
+            h.out_par = par;
+            h.in = par == 0 ? ie + half : ie;
+            h.y = par == 0 ? ie : ie + half;
+            h.out = par == 0 ? oe : oe + half;
+            hipError_t e = launch_hop(h, c.st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    ++c.applies;
+    return partial ? launch_norm2(c.gb, fmt, out, nrhs, partial, c.st) : hipSuccess;
+}
+
+// The CGLS operator: M (even-odd) or D_W (full fields).
+hipError_t apply_a(Ctx& c, int fmt, const void* u, int dagger, const void* in, void* out, void* tmp,
+                   int nrhs, double* partial) {
+    if (c.full) return apply_dw(c, fmt, u, dagger, in, out, nrhs, partial);
+    return apply_m(c, fmt, u, dagger, in, out, tmp, nrhs, partial);
+}
+
 // out = A x for the solver operator (M, or M^dag M through mid); partial = ||out||^2
 // (for M^dag M the partial holds ||M x||^2 only when want_mid_norm).
 hipError_t apply_op(Ctx& c, int op, int fmt, const void* u, const void* x, void* out, void* mid, void* tmp,
                     int nrhs, double* partial) {
-    if (op == WEO_OP_M) return apply_m(c, fmt, u, 0, x, out, tmp, nrhs, partial);
+    if (op != WEO_OP_MDAGM) return apply_a(c, fmt, u, 0, x, out, tmp, nrhs, partial);
     hipError_t e = apply_m(c, fmt, u, 0, x, mid, tmp, nrhs, partial);
     if (e != hipSuccess) return e;
     return apply_m(c, fmt, u, 1, mid, out, tmp, nrhs, nullptr);
@@ -186,23 +230,23 @@ struct LevelResult {
 // live rhs, bb[r] = ||b||^2.  Stops per rhs when ||s||^2 <= tol^2 bb.
 int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const void* u, void* x_acc,
               int nrhs, double tol, int maxiter, int check_every, LevelResult* res) {
-    const Geom& g = c.g;
+    const Geom& g = c.gb;
     // the residual doubles as the operator input when both are stored alike
     const bool same = fmt_info(fmt_op).spinor_prec == fmt_info(fmt_acc).spinor_prec;
     void* s_op = same ? w.s_acc : w.s_op;
-    const uint32_t nbh = hop_partials(g), nbb = blas_blocks(g);
+    const uint32_t nbh = c.nb_apply, nbb = blas_blocks(g);
     ScalarArgsHost sa = sargs(w.sc, nrhs);
     res->iters = 0;
     res->breakdown = 0;
     if (!same) HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_op, s_op, nrhs, nullptr, 0, c.st));
-    if (op == WEO_OP_M) {
+    if (op != WEO_OP_MDAGM) {
         // r = M^dag s, gamma = ||r||^2, p = r
-        HIPCHK(apply_m(c, fmt_op, u, 1, s_op, w.r, w.tmp, nrhs, w.pa));
+        HIPCHK(apply_a(c, fmt_op, u, 1, s_op, w.r, w.tmp, nrhs, w.pa));
     } else {
         HIPCHK(launch_norm2(g, fmt_op, s_op, nrhs, w.pa, c.st));
         HIPCHK(launch_convert(g, fmt_op, s_op, fmt_op, w.r, nrhs, nullptr, 0, c.st));
     }
-    HIPCHK(launch_reduce(w.pa, op == WEO_OP_M ? (int)nbh : (int)nbb, nrhs, w.sc.gamma, c.st));
+    HIPCHK(launch_reduce(w.pa, op != WEO_OP_MDAGM ? (int)nbh : (int)nbb, nrhs, w.sc.gamma, c.st));
     HIPCHK(launch_convert(g, fmt_op, w.r, fmt_op, w.p, nrhs, nullptr, 0, c.st));
 
     std::vector<double> ss(nrhs), bb(nrhs);
@@ -227,8 +271,8 @@ int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const
     }
     for (int it = 1; it <= maxiter; ++it) {
         // q = A p with the alpha denominator in pa
-        if (op == WEO_OP_M) {
-            HIPCHK(apply_m(c, fmt_op, u, 0, w.p, w.q, w.tmp, nrhs, w.pa));
+        if (op != WEO_OP_MDAGM) {
+            HIPCHK(apply_a(c, fmt_op, u, 0, w.p, w.q, w.tmp, nrhs, w.pa));
         } else {
             HIPCHK(apply_op(c, op, fmt_op, u, w.p, w.q, w.t, w.tmp, nrhs, w.pa));
         }
@@ -237,8 +281,8 @@ int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const
         // x += alpha p; s -= alpha q (s is the CG residual r for M^dag M)
         HIPCHK(launch_axpy2(g, fmt_acc, fmt_op, nrhs, w.sc.alpha, w.sc.mask, x_acc, w.p, w.s_acc, w.q,
                             same ? nullptr : s_op, w.pb, c.st));
-        if (op == WEO_OP_M) {
-            HIPCHK(apply_m(c, fmt_op, u, 1, s_op, w.r, w.tmp, nrhs, w.pc));
+        if (op != WEO_OP_MDAGM) {
+            HIPCHK(apply_a(c, fmt_op, u, 1, s_op, w.r, w.tmp, nrhs, w.pc));
             sa.pa = w.pc; sa.nba = (int)nbh; sa.pb = w.pb; sa.nbb = (int)nbb;
             HIPCHK(launch_scalars(SCAL_BETA, sa, c.st));
             HIPCHK(launch_xpay(g, fmt_op, nrhs, w.sc.beta, w.sc.mask, w.r, w.p, c.st));
@@ -272,7 +316,7 @@ int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const
 // True relative residuals ||b - A x|| / ||b|| in format fmt (x, b in fmt).
 int true_resid(Ctx& c, const Workspace& w, int op, int fmt, const void* u, const void* b, const void* x,
                void* t, void* mid, void* tmp, int nrhs, double* out) {
-    const Geom& g = c.g;
+    const Geom& g = c.gb;
     HIPCHK(apply_op(c, op, fmt, u, x, t, mid, tmp, nrhs, nullptr));
     HIPCHK(launch_axpby(g, fmt, nrhs, 1.0, b, -1.0, t, t, w.pa, c.st));
     HIPCHK(launch_reduce(w.pa, (int)blas_blocks(g), nrhs, w.sc.rr, c.st));
@@ -292,9 +336,17 @@ int set_mask(Ctx& c, const Workspace& w, const std::vector<int>& mask) {
     return WEO_OK;
 }
 
+// Geometry of the solver's vectors: the lattice's, or (D_W on full fields)
+// one with twice the sites per field; vector kernels only use the site count.
+Geom vector_geom(const Geom& g, int op) {
+    if (op != WEO_OP_DW) return g;
+    const int d2[4] = {g.lx, g.ly, g.lz, 2 * g.lt};
+    return make_geom(d2);
+}
+
 int check_params(const weo_solver_params* p, int fmt, int* inner_fmt) {
     if (!p) return WEO_ERR_ARG;
-    if (p->op != WEO_OP_M && p->op != WEO_OP_MDAGM) return WEO_ERR_ARG;
+    if (p->op != WEO_OP_M && p->op != WEO_OP_MDAGM && p->op != WEO_OP_DW) return WEO_ERR_ARG;
     if (p->nrhs < 1 || p->nrhs > WEO_MAX_RHS) return WEO_ERR_ARG;
     if (!(p->tol > 0.0) || !std::isfinite(p->tol) || p->maxiter < 0) return WEO_ERR_ARG;
     if (p->check_every < 1 || (p->x0_given != 0 && p->x0_given != 1)) return WEO_ERR_ARG;
@@ -327,7 +379,8 @@ extern "C" size_t wilson_eo_cg_workspace_bytes(const weo_lattice* lat, const weo
     int id, inner;
     if (check_lattice(lat, &g) != WEO_OK || check_fmt(fmt, &id) != WEO_OK) return 0;
     if (check_params(p, id, &inner) != WEO_OK) return 0;
-    return carve_ws(g, id, p, inner, nullptr, 0).bytes;
+    if ((uint64_t)vector_geom(g, p->op).vh > (1ull << 26)) return 0;
+    return carve_ws(vector_geom(g, p->op), id, p, inner, nullptr, 0).bytes;
 }
 
 extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const weo_solver_params* p,
@@ -345,37 +398,42 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
         return rc;
     if (p->mixed && (rc = check_ptr(u_inner)) != WEO_OK) return rc;
     if ((rc = check_ptr(workspace)) != WEO_OK) return rc == WEO_ERR_ARG ? WEO_ERR_WORKSPACE : rc;
-    const Workspace need = carve_ws(g, id, p, inner, nullptr, 0);
+    const Geom gb = vector_geom(g, p->op);
+    if ((uint64_t)gb.vh > (1ull << 26)) return WEO_ERR_DIMS;
+    const Workspace need = carve_ws(gb, id, p, inner, nullptr, 0);
     if (ws_bytes < need.bytes) return WEO_ERR_WORKSPACE;
     const int n = p->nrhs;
-    const size_t fb = (size_t)n * spinor_field_bytes(g, id);
+    const size_t fb = (size_t)n * spinor_field_bytes(gb, id);
     if (overlaps(b, fb, x, fb) || overlaps(workspace, ws_bytes, x, fb) || overlaps(workspace, ws_bytes, b, fb))
         return WEO_ERR_ARG;
 
     std::memset(info, 0, sizeof(*info));
-    Workspace w = carve_ws(g, id, p, inner, static_cast<uint8_t*>(workspace), ws_bytes);
+    Workspace w = carve_ws(gb, id, p, inner, static_cast<uint8_t*>(workspace), ws_bytes);
     Ctx c;
     c.lat = lat;
     c.g = g;
+    c.gb = gb;
+    c.full = p->op == WEO_OP_DW;
+    c.nb_apply = c.full ? blas_blocks(gb) : hop_partials(g);
     phases_of(lat, c.ph);
     c.st = static_cast<hipStream_t>(stream);
     c.applies = 0;
-    const uint32_t nbb = blas_blocks(g);
+    const uint32_t nbb = blas_blocks(gb);
     std::vector<int> live(n, 1);
     int status = WEO_OK;
 
     // bb = ||b||^2
-    HIPCHK(launch_norm2(g, id, b, n, w.pa, c.st));
+    HIPCHK(launch_norm2(gb, id, b, n, w.pa, c.st));
     HIPCHK(launch_reduce(w.pa, (int)nbb, n, w.sc.bb, c.st));
 
     if (!p->mixed) {
         // s = b - A x (or b), x = 0 when no start is given
         if (p->x0_given) {
             HIPCHK(apply_op(c, p->op, id, u, x, w.q, w.t, w.tmp, n, nullptr));
-            HIPCHK(launch_axpby(g, id, n, 1.0, b, -1.0, w.q, w.s_acc, nullptr, c.st));
+            HIPCHK(launch_axpby(gb, id, n, 1.0, b, -1.0, w.q, w.s_acc, nullptr, c.st));
         } else {
             HIPCHK(launch_zero(x, fb, c.st));
-            HIPCHK(launch_convert(g, id, b, id, w.s_acc, n, nullptr, 0, c.st));
+            HIPCHK(launch_convert(gb, id, b, id, w.s_acc, n, nullptr, 0, c.st));
         }
         if ((rc = set_mask(c, w, live)) != WEO_OK) return rc;
         LevelResult lr;
@@ -389,7 +447,7 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
         if (lr.breakdown) status = WEO_BREAKDOWN;
     } else {
         // FP64 defect correction around inner solves in the inner format.
-        const double target = 12.0 * (double)g.vh;    // unit RMS per complex component
+        const double target = 12.0 * (double)gb.vh;    // unit RMS per complex component
         if (!p->x0_given) HIPCHK(launch_zero(x, fb, c.st));
         int inner_iters = 0, k = 0;
         bool breakdown = false;
@@ -397,7 +455,7 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
         for (;;) {
             // r64 = b - A x; rr = ||r64||^2
             HIPCHK(apply_op(c, p->op, id, u, x, w.t64, w.r64, w.tmp64, n, nullptr));
-            HIPCHK(launch_axpby(g, id, n, 1.0, b, -1.0, w.t64, w.r64, w.pa, c.st));
+            HIPCHK(launch_axpby(gb, id, n, 1.0, b, -1.0, w.t64, w.r64, w.pa, c.st));
             ScalarArgsHost sa = sargs(w.sc, n);
             sa.pa = w.pa; sa.nba = (int)nbb; sa.target = target;
             HIPCHK(launch_scalars(SCAL_SCALE, sa, c.st));
@@ -413,8 +471,8 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             }
             if (!nlive || k >= p->max_outer || inner_iters >= p->maxiter || breakdown) break;
             // inner right-hand side: r64 scaled to unit RMS, in FP32; x_acc = 0
-            HIPCHK(launch_convert(g, id, w.r64, kAccF32, w.s_acc, n, w.sc.sc_in, 0, c.st));
-            HIPCHK(launch_zero(w.x_acc, (size_t)n * spinor_field_bytes(g, kAccF32), c.st));
+            HIPCHK(launch_convert(gb, id, w.r64, kAccF32, w.s_acc, n, w.sc.sc_in, 0, c.st));
+            HIPCHK(launch_zero(w.x_acc, (size_t)n * spinor_field_bytes(gb, kAccF32), c.st));
             // the inner stopping test compares with ||rhs||^2 = target
             std::vector<double> tg(n, target);
             HIPCHK(hipMemcpyAsync(w.sc.bb, tg.data(), n * sizeof(double), hipMemcpyHostToDevice, c.st));
@@ -426,9 +484,9 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             inner_iters += lr.iters;
             breakdown = breakdown || lr.breakdown;
             // x += x_acc * sc_out (only live rhs changed: x_acc = 0 elsewhere)
-            HIPCHK(launch_convert(g, kAccF32, w.x_acc, id, x, n, w.sc.sc_out, 1, c.st));
+            HIPCHK(launch_convert(gb, kAccF32, w.x_acc, id, x, n, w.sc.sc_out, 1, c.st));
             // restore ||b||^2
-            HIPCHK(launch_norm2(g, id, b, n, w.pa, c.st));
+            HIPCHK(launch_norm2(gb, id, b, n, w.pa, c.st));
             HIPCHK(launch_reduce(w.pa, (int)nbb, n, w.sc.bb, c.st));
             ++k;
         }

@@ -2,8 +2,10 @@
 
 ``cg`` solves M x = b (CGLS) or M^dag M x = b (CG) for 1..16 packed right-hand
 sides, either in one format or as FP64 defect correction around inner solves
-in a low-precision format.  ``bench_solves``, ``bench_solves_12rhs`` and
-``bench_solves_large`` time the solves the benchmark reports.
+in a low-precision format; op "DW" solves the unpreconditioned D_W x = b on
+full fields (even half then odd half) by CGLS.  ``bench_solves``, ``bench_solves_12rhs`` and
+``bench_solves_large`` time the solves the benchmark reports; ``eo_vs_dw``
+compares the even-odd route with CGLS on the unpreconditioned D_W.
 """
 from __future__ import annotations
 
@@ -14,7 +16,7 @@ import torch
 from . import wilson_eo as W
 from .ops import Format, Lattice, _ptr, _stream
 
-OPS = {"M": W.WEO_OP_M, "MdagM": W.WEO_OP_MDAGM}
+OPS = {"M": W.WEO_OP_M, "MdagM": W.WEO_OP_MDAGM, "DW": W.WEO_OP_DW}
 
 
 def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000, x0=None,
@@ -38,7 +40,7 @@ def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000,
         raise W.WilsonEOError(W.WEO_ERR_ARG, "wilson_eo_cg_workspace_bytes")
     ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
     if out is None:
-        out = lat.new_spinor(fmt, nrhs)
+        out = lat.new_spinor(fmt, 2 * nrhs if op == "DW" else nrhs)
     if x0 is not None:
         out.copy_(x0)
     info = W.weo_solver_info()
@@ -100,7 +102,39 @@ def bench_solves(lat: Lattice, u_np, psi_np, u_dev64, psi_dev64, reps=1):
     base = out["dc_fp32_1e-10"]["seconds"]
     for k in ("dc_bf16_f16link12_1e-10", "dc_f16_f16link12_1e-10"):
         out[k]["speedup_vs_fp32_inner"] = round(base / out[k]["seconds"], 3)
+    out["full_system_fp32_1e-6"] = eo_vs_dw(lat, u32, b32, psi_odd_seed=203)
     return out
+
+
+def eo_vs_dw(lat: Lattice, u32, b_even, psi_odd_seed, tol=1e-6):
+    """The full system D_W xi = eta (eta_e the benchmark source, eta_o a second
+    Gaussian half) in FP32 by CGLS two ways: the even-odd route of Sec. 2
+    (Eq. (4) source, CGLS on M, Eq. (5) odd half) and CGLS on D_W over both
+    parities.  Times include every kernel of each route; both check the
+    residual after every iteration, so the counts are exact."""
+    from . import inputs
+    f32 = Format("f32", "f32", 18)
+    eta_o = lat.pack_spinor(torch.from_numpy(inputs.gen_spinor_half(lat.dims, psi_odd_seed)).cuda(), f32)
+    full = torch.cat([b_even, eta_o])
+    s = lat.spinor_bytes(f32)
+
+    def eo_route():
+        b_e = lat.hop_axpy(u32, full[s:], full[:s], f32, out_parity=0, alpha=lat.kappa)
+        xe, info = cg(lat, f32, u32, b_e, tol=tol, maxiter=20000, check_every=1)
+        lat.hop_axpy(u32, xe, full[s:], f32, out_parity=1, alpha=lat.kappa)
+        return info
+
+    res = {}
+    for name, fn in (("even_odd", eo_route),
+                     ("unpreconditioned_dw", lambda: cg(lat, f32, u32, full, op="DW", tol=tol,
+                                                        maxiter=20000, check_every=1)[1])):
+        fn()                                                   # untimed first call
+        dt, info = _timed(fn)
+        res[name] = {"seconds": round(dt, 4), "iters": info["iters"], "status": info["status"],
+                     "true_rel_resid": info["true_rel_resid"][0]}
+    res["iteration_ratio_dw_over_eo"] = round(res["unpreconditioned_dw"]["iters"] / res["even_odd"]["iters"], 3)
+    res["time_ratio_dw_over_eo"] = round(res["unpreconditioned_dw"]["seconds"] / res["even_odd"]["seconds"], 3)
+    return res
 
 
 def _timed(fn):

@@ -200,3 +200,72 @@ def test_full_system_solve_via_schur(fmt):
     y = eo.clone()
     lat.hop_axpy(u_p, xe, y, fmt, out_parity=1, alpha=kappa, out=y)
     assert torch.equal(same, y)
+
+
+def _full_field(lat, fmt, full):
+    from oracle.lattice import full_to_half
+    e = lat.pack_spinor(to_device(full_to_half(full, 0)), fmt)
+    o = lat.pack_spinor(to_device(full_to_half(full, 1)), fmt)
+    return torch.cat([e, o])
+
+
+def _unpack_full(lat, fmt, x):
+    from oracle.lattice import half_to_full
+    s = lat.spinor_bytes(fmt)
+    e = lat.unpack_spinor(x[:s], fmt).cpu().numpy()
+    o = lat.unpack_spinor(x[s:], fmt).cpu().numpy()
+    return half_to_full(e, 0, lat.dims) + half_to_full(o, 1, lat.dims)
+
+
+def test_unpreconditioned_dw_solve_matches_dense():
+    """CGLS on D_W over both parities (op DW) against a dense FP64 solve."""
+    print("D_W solve 4^4", flush=True)
+    dims, kappa = (4, 4, 4, 4), 0.125
+    lat = Lattice(dims, kappa, AP)
+    u = inputs.gen_gauge(dims, 0.3, 101)
+    eta = inputs.gen_spinor_full(dims, 102)
+    u_p = lat.pack_gauge(to_device(u), F64)
+    b = _full_field(lat, F64, eta)
+    x, info = cg(lat, F64, u_p, b, op="DW", tol=1e-13, maxiter=5000)
+    assert info["status"] == WE.WEO_OK and info["true_rel_resid"][0] <= 1e-13
+    d = W.dense_dirac_wilson(u, kappa, np.array(AP, dtype=np.complex128))
+    xi = np.linalg.solve(d, eta.reshape(-1)).reshape(eta.shape)
+    got = _unpack_full(lat, F64, x)
+    assert rel_err(got, xi) < 1e-11
+    # the oracle's residual of the returned solution
+    r = eta - W.dirac_wilson(u, got, kappa, np.array(AP, dtype=np.complex128))
+    assert np.linalg.norm(r) / np.linalg.norm(eta) < 1e-12
+
+
+@pytest.mark.parametrize("fmt", [F64, F32], ids=["f64", "f32"])
+def test_even_odd_needs_fewer_iterations_than_dw(fmt):
+    """Sec. 2: the even-odd system is better conditioned than D_W, so the same
+    CGLS reaches the same solution in fewer iterations (8^3x16, near-unit
+    links at kappa 0.126).  Both solutions agree on every site."""
+    from oracle.lattice import full_to_half, half_to_full
+    dims, kappa = (8, 8, 8, 16), 0.126
+    tol = 1e-10 if fmt is F64 else 1e-5
+    print(f"eo vs D_W iterations {fmt}", flush=True)
+    lat = Lattice(dims, kappa, AP)
+    u = cached_gauge(dims, 0.5, 850)
+    eta = inputs.gen_spinor_full(dims, 851)
+    u_p = lat.pack_gauge(to_device(u), fmt)
+    b = _full_field(lat, fmt, eta)
+    x_full, info_full = cg(lat, fmt, u_p, b, op="DW", tol=tol, maxiter=20000)
+    s = lat.spinor_bytes(fmt)
+    b_e = lat.hop_axpy(u_p, b[s:], b[:s], fmt, out_parity=0, alpha=kappa)
+    xe, info_eo = cg(lat, fmt, u_p, b_e, tol=tol, maxiter=20000)
+    xo = lat.hop_axpy(u_p, xe, b[s:], fmt, out_parity=1, alpha=kappa)
+    print(f"iterations: D_W {info_full['iters']}, even-odd {info_eo['iters']}", flush=True)
+    assert info_full["status"] == WE.WEO_OK and info_eo["status"] == WE.WEO_OK
+    assert info_eo["iters"] < 0.75 * info_full["iters"]
+    got_full = _unpack_full(lat, fmt, x_full)
+    got_eo = half_to_full(lat.unpack_spinor(xe, fmt).cpu().numpy(), 0, dims) + \
+        half_to_full(lat.unpack_spinor(xo, fmt).cpu().numpy(), 1, dims)
+    assert rel_err(got_eo, got_full) < (1e-8 if fmt is F64 else 1e-4)
+    # both against the oracle's D_W
+    ph = np.array(AP, dtype=np.complex128)
+    eta_r = ROUND[fmt.spinor](eta)
+    for sol in (got_full, got_eo):
+        r = eta_r - W.dirac_wilson(link_as_stored(u, fmt.link, fmt.link_reals), sol, kappa, ph)
+        assert np.linalg.norm(r) / np.linalg.norm(eta_r) < (1e-9 if fmt is F64 else 1e-4)

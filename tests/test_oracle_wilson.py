@@ -227,6 +227,25 @@ def test_schur_determinant_and_solution(dims):
     assert np.abs(xi_o - full_to_half(xi, 1)).max() < 1e-12
 
 
+# --- P5b the even-odd system's spectrum and condition (Sec. 2) ------------------
+
+@pytest.mark.parametrize("kappa,eps", [(0.125, 0.5), (0.15, 0.5), (0.1, 0.9)])
+def test_eo_spectrum_and_condition(kappa, eps):
+    """H maps each parity to the other, so its eigenvalues pair as +-lambda;
+    D_W = 1 - kappa H has 1 - kappa lambda and M = 1 - kappa^2 H_eo H_oe has
+    1 - kappa^2 lambda^2, once per pair.  Sec. 2 states that M is usually
+    better conditioned than D_W: it is on these near-unit configurations."""
+    dims = (4, 4, 2, 2)
+    u = inputs.gen_gauge(dims, eps, 131)
+    d = W.dense_dirac_wilson(u, kappa, PHASES_AP)
+    m = _dense_m(u, kappa, PHASES_AP, dims)
+    ev_d = np.linalg.eigvals(d)
+    from_d = 1 - (1 - ev_d) ** 2                      # each M eigenvalue twice
+    ev_m = np.linalg.eigvals(m)
+    assert _match_multisets(from_d, np.concatenate([ev_m, ev_m])) < 1e-10
+    assert np.linalg.cond(m) < np.linalg.cond(d)
+
+
 # --- P6 single-direction isometry ---------------------------------------------
 
 def test_single_direction_isometry():
