@@ -7,6 +7,8 @@ algorithm.  The oracle uses the standard ones:
 * CGLS (conjugate gradients on the normal equations M^dag M x = M^dag b,
   carrying the residual s = b - M x of the original system) to solve M x = b;
 * CG on the Hermitian positive definite operator A = M^dag M to solve A x = b;
+* BiCGStab (van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992) 631) on M
+  itself, for non-Hermitian M;
 * defect correction (iterative refinement): x += solve(b - M x) with the inner
   solve run to a loose relative tolerance;
 * dense ``numpy.linalg.solve`` on tiny lattices.
@@ -79,6 +81,44 @@ def cg(apply_a, b, tol, maxiter, x0=None):
         p = r + beta * p
         it += 1
         hist.append(np.sqrt(rr) / bnorm)
+    return x, it, hist
+
+
+def bicgstab(apply_a, b, tol, maxiter, x0=None):
+    """Solve A x = b for a general (non-Hermitian) A by BiCGStab.
+
+    Shadow residual r^ = r_0; per iteration two products with A:
+      rho = <r^, r>;  beta = (rho / rho_prev) (alpha / omega)
+      p = r + beta (p - omega v);  v = A p;  alpha = rho / <r^, v>
+      s = r - alpha v;  t = A s;  omega = <t, s> / <t, t>
+      x += alpha p + omega s;  r = s - omega t
+    Stops when the recursive residual ||r|| <= tol ||b||.  Returns (x,
+    iterations, history of ||r||/||b||).
+    """
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - apply_a(x) if x0 is not None else b.copy()
+    rh = r.copy()
+    bnorm = np.sqrt(norm2(b))
+    hist = [np.sqrt(norm2(r)) / bnorm]
+    rho_prev = alpha = omega = 1.0
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    it = 0
+    while hist[-1] > tol and it < maxiter:
+        rho = vdot(rh, r)
+        beta = (rho / rho_prev) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = apply_a(p)
+        alpha = rho / vdot(rh, v)
+        s = r - alpha * v
+        t = apply_a(s)
+        tt = norm2(t)
+        omega = vdot(t, s) / tt if tt > 0 else 0.0
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rho_prev = rho
+        it += 1
+        hist.append(np.sqrt(norm2(r)) / bnorm)
     return x, it, hist
 
 

@@ -69,3 +69,49 @@ def test_cgls_reports_non_convergence_on_singular_operator():
     x, it, hist = S.cgls(m, md, b, 1e-10, 300)
     assert it == 300 and hist[-1] > 1e-3
     assert S.rel_resid(m, x, b) > 1e-3
+
+
+def test_bicgstab_matches_dense_solution():
+    u, b, m, md, dims, kappa = _setup()
+    x, it, hist = S.bicgstab(m, b, 1e-12, 2000)
+    assert hist[-1] <= 1e-12 and it > 3
+    assert S.rel_resid(m, x, b) < 5e-12
+    d = _dense_m(u, kappa, PH, dims)
+    xd = S.dense_solve(d, b.reshape(-1)).reshape(b.shape)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
+    # fewer operator products than CGLS to the same tolerance
+    _, it_cgls, _ = S.cgls(m, md, b, 1e-12, 2000)
+    assert it < it_cgls
+
+
+def test_bicgstab_terminates_by_the_minimal_polynomial():
+    """Without breakdown BiCGStab's residual polynomial contains the BiCG
+    one, so an operator whose minimal polynomial has degree k is solved in
+    at most k iterations (here a non-normal 3-eigenvalue operator, k = 3; a
+    multiple of the identity, k = 1)."""
+    rng = np.random.default_rng(5)
+    n = 24
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam = np.repeat([1.0 + 0.5j, 2.0 - 0.3j, 0.7 + 0.1j], n // 3)
+    sim = q @ (np.eye(n) + 0.3 * rng.standard_normal((n, n)) / np.sqrt(n))   # not unitary
+    a = sim @ np.diag(lam) @ np.linalg.inv(sim)
+    assert np.linalg.norm(a @ a.conj().T - a.conj().T @ a) > 1e-3 * np.linalg.norm(a) ** 2
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, it, hist = S.bicgstab(lambda v: a @ v, b, 1e-12, 50)
+    assert it <= 3 and np.linalg.norm(a @ x - b) / np.linalg.norm(b) < 1e-12
+    x, it, hist = S.bicgstab(lambda v: (2.5 - 1j) * v, b, 1e-14, 50)
+    assert it == 1 and np.linalg.norm((2.5 - 1j) * x - b) / np.linalg.norm(b) < 1e-15
+
+
+def test_bicgstab_iterates_equal_scipy():
+    """Iteration by iteration the oracle's iterate equals SciPy's independent
+    BiCGStab (same start and shadow residual) on a non-normal complex matrix."""
+    import scipy.sparse.linalg as spl
+    rng = np.random.default_rng(3)
+    n = 30
+    a = 2 * np.eye(n) + 0.2 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    for k in (1, 2, 3, 5, 8):
+        x, it, _ = S.bicgstab(lambda v: a @ v, b, 1e-30, k)
+        xs, _ = spl.bicgstab(a, b, x0=np.zeros(n, complex), rtol=1e-30, atol=0.0, maxiter=k)
+        assert it == k and np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-13, k
