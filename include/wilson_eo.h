@@ -231,6 +231,11 @@ int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger,
                              full fields, each the packed even half followed by
                              the packed odd half (2 weo_spinor_bytes(.., 1)) */
 
+#define WEO_SOLVER_CG        0   /* CGLS for WEO_OP_M / WEO_OP_DW, CG for WEO_OP_MDAGM */
+#define WEO_SOLVER_BICGSTAB  1   /* BiCGStab (van der Vorst 1992) on the operator itself:
+                                    two operator products per iteration, complex
+                                    scalars, FP64 dot products */
+
 typedef struct {
     int        op;          /* WEO_OP_M, WEO_OP_MDAGM or WEO_OP_DW */
     int        nrhs;        /* 1..WEO_MAX_RHS right-hand sides solved together */
@@ -244,6 +249,8 @@ typedef struct {
     double     inner_tol;   /* relative tolerance of each inner solve */
     int        max_outer;   /* cap on defect-correction steps */
     int        check_every; /* iterations between host convergence checks (>=1) */
+    int        method;      /* WEO_SOLVER_CG or WEO_SOLVER_BICGSTAB (also for the
+                               inner solves of defect correction) */
 } weo_solver_params;
 
 typedef struct {

@@ -240,6 +240,8 @@ struct ScalarArgs {
     double* sc_in;       // SCAL_SCALE: scale into the inner format
     double* sc_out;      // SCAL_SCALE: scale back
     double* nrm;         // SCAL_SCALE: the reduced norm^2
+    const double* bb;    // SCAL_BETA: ||b||^2 (or null: no device-side stop)
+    double tol2;
 };
 
 __global__ void __launch_bounds__(kRed) k_scalars(int kind, ScalarArgs A) {
@@ -276,6 +278,10 @@ __global__ void __launch_bounds__(kRed) k_scalars(int kind, ScalarArgs A) {
                 A.gamma[r] = a;
             }
             A.ss[r] = A.pb ? b : a;
+            // converged: stop updating this rhs at once (the host sees it at
+            // its next look); iterating on would only push the low-precision
+            // vectors into underflow
+            if (A.bb && A.ss[r] <= A.tol2 * A.bb[r]) A.mask[r] = 0;
         }
         A.beta[r] = be;
     } else {
@@ -284,6 +290,283 @@ __global__ void __launch_bounds__(kRed) k_scalars(int kind, ScalarArgs A) {
         const double si = a > 0.0 ? sqrt(A.target / a) : 1.0;
         A.sc_in[r] = si;
         A.sc_out[r] = 1.0 / si;
+    }
+}
+
+// ---- BiCGStab (van der Vorst 1992) ----------------------------------------------
+// Complex scalars per rhs are (re, im) pairs in FP64 device memory.  Vectors:
+// x, r, r^ (shadow), s in format ACC; p, v, t (and s_op, the operator's copy of
+// s) in format OP.  Masked rhs are left untouched and contribute zero partials.
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 cget(const double* p, int r) { return make_double2(p[2 * r], p[2 * r + 1]); }
+__device__ __forceinline__ void cset(double* p, int r, double2 v) { p[2 * r] = v.x; p[2 * r + 1] = v.y; }
+
+// Sums three values over the workgroup in a fixed order; results in thread 0.
+__device__ __forceinline__ void group_sum3(double a, double b, double c, double* out) {
+    __shared__ double lds[3][16];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    if ((threadIdx.x & 63) == 0) {
+        lds[0][threadIdx.x >> 6] = a;
+        lds[1][threadIdx.x >> 6] = b;
+        lds[2][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = out[1] = out[2] = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            out[0] += lds[0][w];
+            out[1] += lds[1][w];
+            out[2] += lds[2][w];
+        }
+    }
+}
+
+struct BiArgs {
+    double* rho;
+    double* alpha;
+    double* omega;
+    double* beta;
+    double* ss;
+    const double* bb;
+    double tol2;
+    int* mask;
+    int* flags;
+};
+
+__device__ __forceinline__ bool bi_live(const int* mask, int r) { return mask == nullptr || mask[r] != 0; }
+
+// partial <a, b> = sum conj(a) b, a in ACC, b in OP
+template <int ACC, int OP>
+__global__ void __launch_bounds__(kBlk) k_bi_cdot(Fields F, const int* __restrict__ mask, const uint8_t* a,
+                                                  const uint8_t* b, double* pre, double* pim) {
+    using CA = cx<typename AR<ACC>::R>;
+    using CO = cx<typename AR<OP>::R>;
+    const int r = blockIdx.y;
+    const uint32_t i = blockIdx.x * kBlk + threadIdx.x;
+    double re = 0.0, im = 0.0;
+    if (bi_live(mask, r) && i < F.vh) {
+        CA av[12];
+        CO bv[12];
+        load_rec<ACC, 12>(a + (size_t)r * F.fb_acc, F.vh, i, av);
+        load_rec<OP, 12>(b + (size_t)r * F.fb_op, F.vh, i, bv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            re += (double)av[k].x * (double)bv[k].x + (double)av[k].y * (double)bv[k].y;
+            im += (double)av[k].x * (double)bv[k].y - (double)av[k].y * (double)bv[k].x;
+        }
+    }
+    double out[3];
+    group_sum3(re, im, 0.0, out);
+    if (threadIdx.x == 0) {
+        pre[(size_t)r * gridDim.x + blockIdx.x] = out[0];
+        pim[(size_t)r * gridDim.x + blockIdx.x] = out[1];
+    }
+}
+
+// s = r - alpha v  [s_op = s];  partial = ||s||^2
+template <int ACC, int OP, bool SOP>
+__global__ void __launch_bounds__(kBlk) k_bi_s(Fields F, BiArgs B, const uint8_t* rv, const uint8_t* v,
+                                               uint8_t* s, uint8_t* s_op, double* partial) {
+    using RA = typename AR<ACC>::R;
+    using CA = cx<RA>;
+    using CO = cx<typename AR<OP>::R>;
+    const int r = blockIdx.y;
+    const uint32_t i = blockIdx.x * kBlk + threadIdx.x;
+    double nrm = 0.0;
+    if (bi_live(B.mask, r) && i < F.vh) {
+        const double2 al = cget(B.alpha, r);
+        const RA ar = (RA)al.x, ai = (RA)al.y;
+        CA rr[12];
+        CO vv[12];
+        load_rec<ACC, 12>(rv + (size_t)r * F.fb_acc, F.vh, i, rr);
+        load_rec<OP, 12>(v + (size_t)r * F.fb_op, F.vh, i, vv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const RA vx = (RA)vv[k].x, vy = (RA)vv[k].y;
+            rr[k].x = rr[k].x - (ar * vx - ai * vy);
+            rr[k].y = rr[k].y - (ar * vy + ai * vx);
+        }
+        store_rec<ACC, 12>(s + (size_t)r * F.fb_acc, F.vh, i, rr);
+        if constexpr (SOP) {
+            CO so[12];
+            cvt12(rr, so);
+            store_rec<OP, 12>(s_op + (size_t)r * F.fb_op, F.vh, i, so);
+        }
+        nrm = norm2_12(rr);
+    }
+    const double t = group_sum(nrm);
+    if (threadIdx.x == 0) partial[(size_t)r * gridDim.x + blockIdx.x] = t;
+}
+
+// partials <t, s> (re, im) and ||t||^2; t in OP, s in ACC
+template <int ACC, int OP>
+__global__ void __launch_bounds__(kBlk) k_bi_ts(Fields F, const int* __restrict__ mask, const uint8_t* t,
+                                                const uint8_t* s, double* pre, double* pim, double* ptt) {
+    using CA = cx<typename AR<ACC>::R>;
+    using CO = cx<typename AR<OP>::R>;
+    const int r = blockIdx.y;
+    const uint32_t i = blockIdx.x * kBlk + threadIdx.x;
+    double re = 0.0, im = 0.0, tt = 0.0;
+    if (bi_live(mask, r) && i < F.vh) {
+        CO tv[12];
+        CA sv[12];
+        load_rec<OP, 12>(t + (size_t)r * F.fb_op, F.vh, i, tv);
+        load_rec<ACC, 12>(s + (size_t)r * F.fb_acc, F.vh, i, sv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double tx = tv[k].x, ty = tv[k].y, sx = sv[k].x, sy = sv[k].y;
+            re += tx * sx + ty * sy;
+            im += tx * sy - ty * sx;
+            tt += tx * tx + ty * ty;
+        }
+    }
+    double out[3];
+    group_sum3(re, im, tt, out);
+    if (threadIdx.x == 0) {
+        const size_t o = (size_t)r * gridDim.x + blockIdx.x;
+        pre[o] = out[0];
+        pim[o] = out[1];
+        ptt[o] = out[2];
+    }
+}
+
+// x += alpha p + omega s;  r = s - omega t;  partials ||r||^2 and <r^, r>
+template <int ACC, int OP>
+__global__ void __launch_bounds__(kBlk) k_bi_xr(Fields F, BiArgs B, uint8_t* x, const uint8_t* p,
+                                                const uint8_t* s, const uint8_t* t, uint8_t* rv,
+                                                const uint8_t* rh, double* prr, double* pre, double* pim) {
+    using RA = typename AR<ACC>::R;
+    using CA = cx<RA>;
+    using CO = cx<typename AR<OP>::R>;
+    const int r = blockIdx.y;
+    const uint32_t i = blockIdx.x * kBlk + threadIdx.x;
+    double nrm = 0.0, re = 0.0, im = 0.0;
+    if (bi_live(B.mask, r) && i < F.vh) {
+        const double2 al = cget(B.alpha, r), om = cget(B.omega, r);
+        const RA ar = (RA)al.x, ai = (RA)al.y, wr = (RA)om.x, wi = (RA)om.y;
+        CA xv[12], sv[12];
+        CO pv[12], tv[12];
+        uint8_t* xrow = x + (size_t)r * F.fb_acc;
+        load_rec<ACC, 12>(xrow, F.vh, i, xv);
+        load_rec<OP, 12>(p + (size_t)r * F.fb_op, F.vh, i, pv);
+        load_rec<ACC, 12>(s + (size_t)r * F.fb_acc, F.vh, i, sv);
+        load_rec<OP, 12>(t + (size_t)r * F.fb_op, F.vh, i, tv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const RA px = (RA)pv[k].x, py = (RA)pv[k].y, tx = (RA)tv[k].x, ty = (RA)tv[k].y;
+            xv[k].x += (ar * px - ai * py) + (wr * sv[k].x - wi * sv[k].y);
+            xv[k].y += (ar * py + ai * px) + (wr * sv[k].y + wi * sv[k].x);
+            sv[k].x -= wr * tx - wi * ty;          // sv becomes the new r
+            sv[k].y -= wr * ty + wi * tx;
+        }
+        store_rec<ACC, 12>(xrow, F.vh, i, xv);
+        store_rec<ACC, 12>(rv + (size_t)r * F.fb_acc, F.vh, i, sv);
+        CA hv[12];
+        load_rec<ACC, 12>(rh + (size_t)r * F.fb_acc, F.vh, i, hv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double hx = hv[k].x, hy = hv[k].y, rx = sv[k].x, ry = sv[k].y;
+            nrm += rx * rx + ry * ry;
+            re += hx * rx + hy * ry;
+            im += hx * ry - hy * rx;
+        }
+    }
+    double out[3];
+    group_sum3(nrm, re, im, out);
+    if (threadIdx.x == 0) {
+        const size_t o = (size_t)r * gridDim.x + blockIdx.x;
+        prr[o] = out[0];
+        pre[o] = out[1];
+        pim[o] = out[2];
+    }
+}
+
+// p = r + beta (p - omega v);  r in ACC, p and v in OP
+template <int ACC, int OP>
+__global__ void __launch_bounds__(kBlk) k_bi_p(Fields F, BiArgs B, const uint8_t* rv, uint8_t* p,
+                                               const uint8_t* v) {
+    using RA = typename AR<ACC>::R;
+    using CA = cx<RA>;
+    using CO = cx<typename AR<OP>::R>;
+    const int r = blockIdx.y;
+    const uint32_t i = blockIdx.x * kBlk + threadIdx.x;
+    if (!bi_live(B.mask, r) || i >= F.vh) return;
+    const double2 be = cget(B.beta, r), om = cget(B.omega, r);
+    const RA br = (RA)be.x, bi = (RA)be.y, wr = (RA)om.x, wi = (RA)om.y;
+    CA rr[12];
+    CO pv[12], vv[12];
+    uint8_t* prow = p + (size_t)r * F.fb_op;
+    load_rec<ACC, 12>(rv + (size_t)r * F.fb_acc, F.vh, i, rr);
+    load_rec<OP, 12>(prow, F.vh, i, pv);
+    load_rec<OP, 12>(v + (size_t)r * F.fb_op, F.vh, i, vv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const RA vx = (RA)vv[k].x, vy = (RA)vv[k].y;
+        const RA dx = (RA)pv[k].x - (wr * vx - wi * vy);
+        const RA dy = (RA)pv[k].y - (wr * vy + wi * vx);
+        rr[k].x += br * dx - bi * dy;
+        rr[k].y += br * dy + bi * dx;
+    }
+    CO po[12];
+    cvt12(rr, po);
+    store_rec<OP, 12>(prow, F.vh, i, po);
+}
+
+// Scalar steps, one workgroup per rhs; pa, pb, pc are [nrhs][nb] partials.
+//   BI_INIT:  pa = ||r||^2        -> rho = ||r||^2, ss = ||r||^2, alpha = omega = 1
+//   BI_ALPHA: pa, pb = <r^, v>     -> alpha = rho / <r^, v>
+//   BI_OMEGA: pa, pb = <t, s>, pc = ||t||^2 -> omega = <t, s> / ||t||^2 (0 if t = 0)
+//   BI_BETA:  pa = ||r||^2, pb, pc = <r^, r> -> ss, beta = (rho'/rho)(alpha/omega), rho = rho'
+// ||r||^2 <= tol2 ||b||^2 masks the rhs off (converged, also for b = 0); a
+// vanishing or non-finite denominator is a breakdown (flag, masked off).
+__global__ void __launch_bounds__(kRed) k_bi_scalars(int kind, BiArgs B, int nb, const double* pa,
+                                                     const double* pb, const double* pc) {
+    const int r = blockIdx.x;
+    const double a = reduce_row(pa + (size_t)r * nb, nb);
+    const double b = pb ? reduce_row(pb + (size_t)r * nb, nb) : 0.0;
+    const double c = pc ? reduce_row(pc + (size_t)r * nb, nb) : 0.0;
+    if (threadIdx.x != 0) return;
+    if (!bi_live(B.mask, r)) return;
+    auto fail = [&]() { B.flags[r] |= 1; B.mask[r] = 0; };
+    if (kind == BI_INIT) {
+        cset(B.rho, r, make_double2(a, 0.0));
+        cset(B.alpha, r, make_double2(1.0, 0.0));
+        cset(B.omega, r, make_double2(1.0, 0.0));
+        cset(B.beta, r, make_double2(0.0, 0.0));
+        B.ss[r] = a;
+        if (!isfinite(a)) fail();
+        else if (a <= B.tol2 * B.bb[r]) B.mask[r] = 0;      // includes b = 0
+    } else if (kind == BI_ALPHA) {
+        const double2 d = make_double2(a, b);
+        if (!(d.x * d.x + d.y * d.y > 0.0) || !isfinite(d.x) || !isfinite(d.y)) { fail(); return; }
+        cset(B.alpha, r, cdiv(cget(B.rho, r), d));
+    } else if (kind == BI_OMEGA) {
+        if (!isfinite(a) || !isfinite(b) || !isfinite(c)) { fail(); return; }
+        cset(B.omega, r, c > 0.0 ? make_double2(a / c, b / c) : make_double2(0.0, 0.0));
+    } else {
+        B.ss[r] = a;
+        if (isfinite(a) && a <= B.tol2 * B.bb[r]) {      // converged (or exact)
+            cset(B.beta, r, make_double2(0.0, 0.0));
+            B.mask[r] = 0;
+            return;
+        }
+        const double2 rn = make_double2(b, c), rho = cget(B.rho, r), om = cget(B.omega, r);
+        if (!isfinite(a) || !isfinite(b) || !isfinite(c) || !(om.x * om.x + om.y * om.y > 0.0) ||
+            !(rho.x * rho.x + rho.y * rho.y > 0.0)) {
+            fail();
+            return;
+        }
+        cset(B.beta, r, cmul(cdiv(rn, rho), cdiv(cget(B.alpha, r), om)));
+        cset(B.rho, r, rn);
     }
 }
 
@@ -417,7 +700,102 @@ hipError_t launch_scalars(int kind, const ScalarArgsHost& h, hipStream_t st) {
     A.gamma = h.gamma; A.alpha = h.alpha; A.beta = h.beta; A.ss = h.ss;
     A.mask = h.mask; A.flags = h.flags; A.target = h.target;
     A.sc_in = h.sc_in; A.sc_out = h.sc_out; A.nrm = h.nrm;
+    A.bb = h.bb; A.tol2 = h.tol2;
     hipLaunchKernelGGL(k_scalars, dim3(h.nrhs), dim3(kRed), 0, st, kind, A);
+    return hipGetLastError();
+}
+
+}  // namespace weo
+
+namespace weo {
+
+static BiArgs bi_args(const BiScalHost& h) {
+    BiArgs B;
+    B.rho = h.rho; B.alpha = h.alpha; B.omega = h.omega; B.beta = h.beta;
+    B.ss = h.ss; B.bb = h.bb; B.tol2 = h.tol2; B.mask = h.mask; B.flags = h.flags;
+    return B;
+}
+
+// Dispatch over the (acc, op) storage pairs the solvers use.
+#define WEO_BI_PAIRS(ACCP, OPP, CALL)                                                         \
+    if (ACCP == P_F64 && OPP == P_F64) { constexpr int A_ = P_F64, O_ = P_F64; CALL; }        \
+    else if (ACCP == P_F32 && OPP == P_F32) { constexpr int A_ = P_F32, O_ = P_F32; CALL; }   \
+    else if (ACCP == P_F32 && OPP == P_F16) { constexpr int A_ = P_F32, O_ = P_F16; CALL; }   \
+    else if (ACCP == P_F32 && OPP == P_BF16) { constexpr int A_ = P_F32, O_ = P_BF16; CALL; } \
+    else return hipErrorInvalidValue;
+
+hipError_t launch_bi_cdot(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const int* mask, const void* a,
+                          const void* b, double* pre, double* pim, hipStream_t st) {
+    const Fields F = fields(g, fmt_acc, fmt_op);
+    const dim3 grid(blas_blocks(g), nrhs), block(kBlk);
+    auto* A = static_cast<const uint8_t*>(a);
+    auto* Bv = static_cast<const uint8_t*>(b);
+    WEO_BI_PAIRS(sp_of(fmt_acc), sp_of(fmt_op),
+                 hipLaunchKernelGGL((k_bi_cdot<A_, O_>), grid, block, 0, st, F, mask, A, Bv, pre, pim))
+    return hipGetLastError();
+}
+
+hipError_t launch_bi_s(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const BiScalHost& h, const void* r,
+                       const void* v, void* s, void* s_op, double* partial, hipStream_t st) {
+    const Fields F = fields(g, fmt_acc, fmt_op);
+    const dim3 grid(blas_blocks(g), nrhs), block(kBlk);
+    const BiArgs B = bi_args(h);
+    auto* R = static_cast<const uint8_t*>(r);
+    auto* V = static_cast<const uint8_t*>(v);
+    auto* S = static_cast<uint8_t*>(s);
+    auto* SO = static_cast<uint8_t*>(s_op);
+    const bool sop = sp_of(fmt_acc) != sp_of(fmt_op);
+    WEO_BI_PAIRS(sp_of(fmt_acc), sp_of(fmt_op),
+                 if (sop) hipLaunchKernelGGL((k_bi_s<A_, O_, true>), grid, block, 0, st, F, B, R, V, S, SO, partial);
+                 else hipLaunchKernelGGL((k_bi_s<A_, O_, false>), grid, block, 0, st, F, B, R, V, S, SO, partial))
+    return hipGetLastError();
+}
+
+hipError_t launch_bi_ts(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const int* mask, const void* t,
+                        const void* s, double* pre, double* pim, double* ptt, hipStream_t st) {
+    const Fields F = fields(g, fmt_acc, fmt_op);
+    const dim3 grid(blas_blocks(g), nrhs), block(kBlk);
+    auto* T = static_cast<const uint8_t*>(t);
+    auto* S = static_cast<const uint8_t*>(s);
+    WEO_BI_PAIRS(sp_of(fmt_acc), sp_of(fmt_op),
+                 hipLaunchKernelGGL((k_bi_ts<A_, O_>), grid, block, 0, st, F, mask, T, S, pre, pim, ptt))
+    return hipGetLastError();
+}
+
+hipError_t launch_bi_xr(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const BiScalHost& h, void* x,
+                        const void* p, const void* s, const void* t, void* r, const void* rh, double* prr,
+                        double* pre, double* pim, hipStream_t st) {
+    const Fields F = fields(g, fmt_acc, fmt_op);
+    const dim3 grid(blas_blocks(g), nrhs), block(kBlk);
+    const BiArgs B = bi_args(h);
+    auto* X = static_cast<uint8_t*>(x);
+    auto* Pp = static_cast<const uint8_t*>(p);
+    auto* S = static_cast<const uint8_t*>(s);
+    auto* T = static_cast<const uint8_t*>(t);
+    auto* R = static_cast<uint8_t*>(r);
+    auto* RH = static_cast<const uint8_t*>(rh);
+    WEO_BI_PAIRS(sp_of(fmt_acc), sp_of(fmt_op),
+                 hipLaunchKernelGGL((k_bi_xr<A_, O_>), grid, block, 0, st, F, B, X, Pp, S, T, R, RH, prr, pre, pim))
+    return hipGetLastError();
+}
+
+hipError_t launch_bi_p(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const BiScalHost& h, const void* r,
+                       void* p, const void* v, hipStream_t st) {
+    const Fields F = fields(g, fmt_acc, fmt_op);
+    const dim3 grid(blas_blocks(g), nrhs), block(kBlk);
+    const BiArgs B = bi_args(h);
+    auto* R = static_cast<const uint8_t*>(r);
+    auto* Pp = static_cast<uint8_t*>(p);
+    auto* V = static_cast<const uint8_t*>(v);
+    WEO_BI_PAIRS(sp_of(fmt_acc), sp_of(fmt_op),
+                 hipLaunchKernelGGL((k_bi_p<A_, O_>), grid, block, 0, st, F, B, R, Pp, V))
+    return hipGetLastError();
+}
+#undef WEO_BI_PAIRS
+
+hipError_t launch_bi_scalars(int kind, const BiScalHost& h, int nb, const double* pa, const double* pb,
+                             const double* pc, hipStream_t st) {
+    hipLaunchKernelGGL(k_bi_scalars, dim3(h.nrhs), dim3(kRed), 0, st, kind, bi_args(h), nb, pa, pb, pc);
     return hipGetLastError();
 }
 

@@ -15,6 +15,12 @@
 //     r = b - A x;  p = r;  gamma = <r, r>
 //     repeat: t = M p;  q = M^dag t;  alpha = gamma / ||t||^2;  x += alpha p;
 //             r -= alpha q;  beta = <r, r> / gamma;  gamma = <r, r>;  p = r + beta p
+//  BiCGStab (van der Vorst 1992) for A x = b, any of the operators above
+//  (method WEO_SOLVER_BICGSTAB), shadow residual r^ = r_0, two products with
+//  A per iteration and complex scalars:
+//     v = A p;  alpha = rho / <r^, v>;  s = r - alpha v;  t = A s;
+//     omega = <t, s> / ||t||^2;  x += alpha p + omega s;  r = s - omega t;
+//     rho' = <r^, r>;  beta = (rho' / rho)(alpha / omega);  p = r + beta (p - omega v)
 //  Defect correction (mixed precision): in FP64, r = b - A x; the residual is
 //  rescaled to unit RMS component, solved approximately in the inner format
 //  (relative tolerance inner_tol) and the correction added back in FP64.
@@ -64,12 +70,14 @@ struct Carve {
 // Device scalar block: one entry per rhs for each quantity.
 struct Scalars {
     double *gamma, *alpha, *beta, *ss, *bb, *rr, *sc_in, *sc_out, *nrm;
+    double *crho, *calpha, *comega, *cbeta;     // BiCGStab complex scalars (re, im)
     int *mask, *flags;
 };
 
 struct Workspace {
     // fields (nrhs each)
     void *s_acc, *x_acc, *s_op, *p, *q, *r, *t, *tmp;     // level vectors
+    void *rh, *s2;                                        // BiCGStab: shadow residual, s (acc)
     void *r64, *t64, *tmp64;                              // outer (mixed) vectors
     double *pa, *pb, *pc;                                 // partial sums
     Scalars sc;
@@ -103,6 +111,10 @@ Workspace carve_ws(const Geom& g, int fmt, const weo_solver_params* p, int inner
     w.r = c.take(fo);
     w.t = c.take(fo);
     w.tmp = c.take(fo);
+    if (p->method == WEO_SOLVER_BICGSTAB) {
+        w.rh = c.take(fa);
+        w.s2 = c.take(fa);
+    }
     if (p->mixed) {
         const size_t f64 = (size_t)n * spinor_field_bytes(g, fmt);
         w.r64 = c.take(f64);
@@ -113,11 +125,12 @@ Workspace carve_ws(const Geom& g, int fmt, const weo_solver_params* p, int inner
     w.pa = static_cast<double*>(c.take(np));
     w.pb = static_cast<double*>(c.take(np));
     w.pc = static_cast<double*>(c.take(np));
-    double* d = static_cast<double*>(c.take(9 * WEO_MAX_RHS * sizeof(double)));
+    double* d = static_cast<double*>(c.take(17 * WEO_MAX_RHS * sizeof(double)));
     int* ip = static_cast<int*>(c.take(2 * WEO_MAX_RHS * sizeof(int)));
     if (d) {
         w.sc.gamma = d; w.sc.alpha = d + 16; w.sc.beta = d + 32; w.sc.ss = d + 48; w.sc.bb = d + 64;
         w.sc.rr = d + 80; w.sc.sc_in = d + 96; w.sc.sc_out = d + 112; w.sc.nrm = d + 128;
+        w.sc.crho = d + 144; w.sc.calpha = d + 176; w.sc.comega = d + 208; w.sc.cbeta = d + 240;
         w.sc.mask = ip; w.sc.flags = ip + 16;
     }
     w.bytes = c.off;
@@ -225,6 +238,60 @@ struct LevelResult {
     int breakdown;
 };
 
+// Host look at the residual norms: masks off converged rhs, notes breakdowns.
+// Returns the number of live rhs (or a negative status); ss and mask are
+// left holding what was seen.
+int look_at(Ctx& c, const Workspace& w, int nrhs, double tol2, const std::vector<double>& bb,
+            std::vector<double>& ss, std::vector<int>& mask, LevelResult* res) {
+    std::vector<int> flags(nrhs);
+    HIPCHK(hipMemcpyAsync(ss.data(), w.sc.ss, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(mask.data(), w.sc.mask, nrhs * sizeof(int), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(flags.data(), w.sc.flags, nrhs * sizeof(int), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    int live = 0;
+    bool changed = false;
+    for (int r = 0; r < nrhs; ++r) {
+        if (flags[r]) res->breakdown = 1;
+        if (mask[r] && ss[r] <= tol2 * bb[r]) { mask[r] = 0; changed = true; }
+        live += mask[r] != 0;
+    }
+    if (changed) {
+        HIPCHK(hipMemcpyAsync(w.sc.mask, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));     // the host vector goes out of scope
+    }
+    return live;
+}
+
+// When the host next looks at the residuals.  The look costs a stream
+// synchronisation, so it is not done every iteration: after a look the
+// convergence rate of each live rhs since the previous look predicts the
+// iteration at which the slowest one reaches its tolerance, and the next look
+// is placed there (at most check_every iterations ahead; the first look after
+// two iterations).  Converged rhs are masked off on the device as soon as
+// their residual passes, so a late look only costs masked-off iterations.
+struct LookPlan {
+    int every, last_it = 0;
+    std::vector<double> last_ss;
+    LookPlan(int check_every, const std::vector<double>& ss0) : every(check_every), last_ss(ss0) {}
+    int first() const { return every < 2 ? every : 2; }
+    int next(int it, const std::vector<double>& ss, const std::vector<int>& mask, const std::vector<double>& bb,
+             double tol2) {
+        double need = 1.0;
+        for (size_t r = 0; r < ss.size(); ++r) {
+            if (!mask[r]) continue;
+            const double a = last_ss[r], b = ss[r], goal = tol2 * bb[r];
+            if (!(a > 0.0) || !(b > 0.0) || !(b < a) || it <= last_it) { need = every; break; }
+            const double rate = std::log(b / a) / (double)(it - last_it);   // per iteration, < 0
+            const double k = std::log(goal / b) / rate;
+            if (k > need) need = k;
+        }
+        last_ss = ss;
+        last_it = it;
+        const int k = need >= (double)every ? every : (int)std::ceil(need);
+        return it + (k < 1 ? 1 : k);
+    }
+};
+
 // Iterate one precision level.  On entry: x_acc holds the start (zero or x0),
 // s_acc the matching residual (b - M x for CGLS, b - A x for CG), mask the
 // live rhs, bb[r] = ||b||^2.  Stops per rhs when ||s||^2 <= tol^2 bb.
@@ -236,6 +303,8 @@ int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const
     void* s_op = same ? w.s_acc : w.s_op;
     const uint32_t nbh = c.nb_apply, nbb = blas_blocks(g);
     ScalarArgsHost sa = sargs(w.sc, nrhs);
+    sa.bb = w.sc.bb;
+    sa.tol2 = tol * tol;
     res->iters = 0;
     res->breakdown = 0;
     if (!same) HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_op, s_op, nrhs, nullptr, 0, c.st));
@@ -250,7 +319,7 @@ int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const
     HIPCHK(launch_convert(g, fmt_op, w.r, fmt_op, w.p, nrhs, nullptr, 0, c.st));
 
     std::vector<double> ss(nrhs), bb(nrhs);
-    std::vector<int> mask(nrhs), flags(nrhs);
+    std::vector<int> mask(nrhs);
     const double tol2 = tol * tol;
     // a start that already meets the tolerance costs no iteration
     HIPCHK(launch_norm2(g, fmt_acc, w.s_acc, nrhs, w.pb, c.st));
@@ -269,6 +338,8 @@ int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const
         HIPCHK(hipStreamSynchronize(c.st));
         if (!live) return WEO_OK;
     }
+    LookPlan plan(check_every, ss);
+    int look = plan.first();
     for (int it = 1; it <= maxiter; ++it) {
         // q = A p with the alpha denominator in pa
         if (op != WEO_OP_MDAGM) {
@@ -292,25 +363,78 @@ int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const
             HIPCHK(launch_xpay(g, fmt_op, nrhs, w.sc.beta, w.sc.mask, s_op, w.p, c.st));
         }
         res->iters = it;
-        if (it % check_every == 0 || it == maxiter) {
-            HIPCHK(hipMemcpyAsync(ss.data(), w.sc.ss, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
-            HIPCHK(hipMemcpyAsync(mask.data(), w.sc.mask, nrhs * sizeof(int), hipMemcpyDeviceToHost, c.st));
-            HIPCHK(hipMemcpyAsync(flags.data(), w.sc.flags, nrhs * sizeof(int), hipMemcpyDeviceToHost, c.st));
-            HIPCHK(hipStreamSynchronize(c.st));
-            int live = 0;
-            bool changed = false;
-            for (int r = 0; r < nrhs; ++r) {
-                if (flags[r]) res->breakdown = 1;
-                if (mask[r] && ss[r] <= tol2 * bb[r]) { mask[r] = 0; changed = true; }
-                live += mask[r] != 0;
-            }
-            if (changed)
-                HIPCHK(hipMemcpyAsync(w.sc.mask, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c.st));
+        if (it == look || it == maxiter) {
+            const int live = look_at(c, w, nrhs, tol2, bb, ss, mask, res);
+            if (live < 0) return live;
             if (!live) break;
+            look = plan.next(it, ss, mask, bb, tol2);
         }
     }
     HIPCHK(hipStreamSynchronize(c.st));
     return WEO_OK;
+}
+
+// BiCGStab at one precision level.  Same contract as run_level: x_acc holds
+// the start, s_acc the matching residual b - A x, mask the live rhs and
+// bb[r] = ||b||^2; stops per rhs when ||r||^2 <= tol^2 bb.  Vectors: r = s_acc,
+// r^ = rh, s = s2 (all fmt_acc); p, v = q, t, s_op, mid = r (fmt_op).
+int run_level_bicg(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const void* u, void* x_acc,
+                   int nrhs, double tol, int maxiter, int check_every, LevelResult* res) {
+    const Geom& g = c.gb;
+    const bool same = fmt_info(fmt_op).spinor_prec == fmt_info(fmt_acc).spinor_prec;
+    void* s_op = same ? w.s2 : w.s_op;
+    const int nbb = (int)blas_blocks(g);
+    const double tol2 = tol * tol;
+    BiScalHost B;
+    B.nrhs = nrhs;
+    B.rho = w.sc.crho; B.alpha = w.sc.calpha; B.omega = w.sc.comega; B.beta = w.sc.cbeta;
+    B.ss = w.sc.ss; B.bb = w.sc.bb; B.tol2 = tol2; B.mask = w.sc.mask; B.flags = w.sc.flags;
+    res->iters = 0;
+    res->breakdown = 0;
+    std::vector<double> ss(nrhs);
+    std::vector<int> mask(nrhs);
+    std::vector<double> bb(nrhs);
+    HIPCHK(hipMemcpyAsync(bb.data(), w.sc.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    // r^ = r, p = r, rho = ||r||^2
+    HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_acc, w.rh, nrhs, nullptr, 0, c.st));
+    HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_op, w.p, nrhs, nullptr, 0, c.st));
+    HIPCHK(launch_norm2(g, fmt_acc, w.s_acc, nrhs, w.pa, c.st));
+    HIPCHK(launch_bi_scalars(BI_INIT, B, nbb, w.pa, nullptr, nullptr, c.st));
+    int live = look_at(c, w, nrhs, tol2, bb, ss, mask, res);
+    if (live < 0) return live;
+    if (!live) return WEO_OK;
+    LookPlan plan(check_every, ss);
+    int look = plan.first();
+    for (int it = 1; it <= maxiter; ++it) {
+        HIPCHK(apply_op(c, op, fmt_op, u, w.p, w.q, w.r, w.tmp, nrhs, nullptr));
+        HIPCHK(launch_bi_cdot(g, fmt_acc, fmt_op, nrhs, w.sc.mask, w.rh, w.q, w.pa, w.pb, c.st));
+        HIPCHK(launch_bi_scalars(BI_ALPHA, B, nbb, w.pa, w.pb, nullptr, c.st));
+        HIPCHK(launch_bi_s(g, fmt_acc, fmt_op, nrhs, B, w.s_acc, w.q, w.s2, s_op, w.pc, c.st));
+        HIPCHK(apply_op(c, op, fmt_op, u, s_op, w.t, w.r, w.tmp, nrhs, nullptr));
+        HIPCHK(launch_bi_ts(g, fmt_acc, fmt_op, nrhs, w.sc.mask, w.t, w.s2, w.pa, w.pb, w.pc, c.st));
+        HIPCHK(launch_bi_scalars(BI_OMEGA, B, nbb, w.pa, w.pb, w.pc, c.st));
+        HIPCHK(launch_bi_xr(g, fmt_acc, fmt_op, nrhs, B, x_acc, w.p, w.s2, w.t, w.s_acc, w.rh, w.pa, w.pb,
+                            w.pc, c.st));
+        HIPCHK(launch_bi_scalars(BI_BETA, B, nbb, w.pa, w.pb, w.pc, c.st));
+        HIPCHK(launch_bi_p(g, fmt_acc, fmt_op, nrhs, B, w.s_acc, w.p, w.q, c.st));
+        res->iters = it;
+        if (it == look || it == maxiter) {
+            live = look_at(c, w, nrhs, tol2, bb, ss, mask, res);
+            if (live < 0) return live;
+            if (!live) break;
+            look = plan.next(it, ss, mask, bb, tol2);
+        }
+    }
+    HIPCHK(hipStreamSynchronize(c.st));
+    return WEO_OK;
+}
+
+// One precision level with the requested method.
+int run_method(Ctx& c, const Workspace& w, int method, int op, int fmt_op, int fmt_acc, const void* u,
+               void* x_acc, int nrhs, double tol, int maxiter, int check_every, LevelResult* res) {
+    if (method == WEO_SOLVER_BICGSTAB)
+        return run_level_bicg(c, w, op, fmt_op, fmt_acc, u, x_acc, nrhs, tol, maxiter, check_every, res);
+    return run_level(c, w, op, fmt_op, fmt_acc, u, x_acc, nrhs, tol, maxiter, check_every, res);
 }
 
 // True relative residuals ||b - A x|| / ||b|| in format fmt (x, b in fmt).
@@ -351,6 +475,7 @@ int check_params(const weo_solver_params* p, int fmt, int* inner_fmt) {
     if (!(p->tol > 0.0) || !std::isfinite(p->tol) || p->maxiter < 0) return WEO_ERR_ARG;
     if (p->check_every < 1 || (p->x0_given != 0 && p->x0_given != 1)) return WEO_ERR_ARG;
     if (p->mixed != 0 && p->mixed != 1) return WEO_ERR_ARG;
+    if (p->method != WEO_SOLVER_CG && p->method != WEO_SOLVER_BICGSTAB) return WEO_ERR_ARG;
     *inner_fmt = fmt;
     if (p->mixed) {
         if (fmt_info(fmt).spinor_prec != WEO_F64) return WEO_ERR_FORMAT;
@@ -437,7 +562,8 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
         }
         if ((rc = set_mask(c, w, live)) != WEO_OK) return rc;
         LevelResult lr;
-        if ((rc = run_level(c, w, p->op, id, id, u, x, n, p->tol, p->maxiter, p->check_every, &lr)) != WEO_OK)
+        if ((rc = run_method(c, w, p->method, p->op, id, id, u, x, n, p->tol, p->maxiter, p->check_every,
+                             &lr)) != WEO_OK)
             return rc;
         info->iters = lr.iters;
         if ((rc = true_resid(c, w, p->op, id, u, b, x, w.q, w.t, w.tmp, n, info->true_rel_resid)) != WEO_OK)
@@ -478,8 +604,8 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             HIPCHK(hipMemcpyAsync(w.sc.bb, tg.data(), n * sizeof(double), hipMemcpyHostToDevice, c.st));
             if ((rc = set_mask(c, w, live)) != WEO_OK) return rc;
             LevelResult lr;
-            if ((rc = run_level(c, w, p->op, inner, kAccF32, u_inner, w.x_acc, n, p->inner_tol,
-                                p->maxiter - inner_iters, p->check_every, &lr)) != WEO_OK)
+            if ((rc = run_method(c, w, p->method, p->op, inner, kAccF32, u_inner, w.x_acc, n, p->inner_tol,
+                                 p->maxiter - inner_iters, p->check_every, &lr)) != WEO_OK)
                 return rc;
             inner_iters += lr.iters;
             breakdown = breakdown || lr.breakdown;

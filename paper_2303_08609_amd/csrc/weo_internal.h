@@ -115,8 +115,46 @@ struct ScalarArgsHost {
     double* sc_in;
     double* sc_out;
     double* nrm;
+    const double* bb;   // SCAL_BETA: ||b||^2 per rhs; ss <= tol2 bb masks the rhs off
+    double tol2;
 };
 hipError_t launch_scalars(int kind, const ScalarArgsHost& a, hipStream_t s);
+
+// ---- BiCGStab vector and scalar steps ---------------------------------------
+// Complex per-rhs scalars are (re, im) pairs of doubles in device memory.
+// x, r, r^, s in fmt_acc; p, v, t, s_op in fmt_op (s_op written only when
+// the two formats store spinors differently).  Partials are [nrhs][blas_blocks].
+enum { BI_INIT = 0, BI_ALPHA = 1, BI_OMEGA = 2, BI_BETA = 3 };
+struct BiScalHost {
+    int nrhs;
+    double* rho;
+    double* alpha;
+    double* omega;
+    double* beta;
+    double* ss;      // ||r||^2 for the host's convergence check
+    const double* bb;  // ||b||^2 per rhs: ||r||^2 <= tol2 bb masks the rhs off
+    double tol2;
+    int* mask;
+    int* flags;
+};
+// partials of <a, b> (a in fmt_acc, b in fmt_op)
+hipError_t launch_bi_cdot(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const int* mask, const void* a,
+                          const void* b, double* pre, double* pim, hipStream_t st);
+// s = r - alpha v, s_op = s, partial ||s||^2
+hipError_t launch_bi_s(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const BiScalHost& h, const void* r,
+                       const void* v, void* s, void* s_op, double* partial, hipStream_t st);
+// partials of <t, s> and ||t||^2
+hipError_t launch_bi_ts(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const int* mask, const void* t,
+                        const void* s, double* pre, double* pim, double* ptt, hipStream_t st);
+// x += alpha p + omega s, r = s - omega t, partials ||r||^2 and <r^, r>
+hipError_t launch_bi_xr(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const BiScalHost& h, void* x,
+                        const void* p, const void* s, const void* t, void* r, const void* rh, double* prr,
+                        double* pre, double* pim, hipStream_t st);
+// p = r + beta (p - omega v)
+hipError_t launch_bi_p(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const BiScalHost& h, const void* r,
+                       void* p, const void* v, hipStream_t st);
+hipError_t launch_bi_scalars(int kind, const BiScalHost& h, int nb, const double* pa, const double* pb,
+                             const double* pc, hipStream_t st);
 
 // ---- pack / unpack --------------------------------------------------------
 hipError_t launch_pack_gauge(const Geom& g, int fmt, const void* canon, int canon_f64,

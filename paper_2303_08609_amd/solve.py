@@ -19,10 +19,14 @@ from .ops import Format, Lattice, _ptr, _stream
 OPS = {"M": W.WEO_OP_M, "MdagM": W.WEO_OP_MDAGM, "DW": W.WEO_OP_DW}
 
 
+METHODS = {"cg": W.WEO_SOLVER_CG, "bicgstab": W.WEO_SOLVER_BICGSTAB}
+
+
 def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000, x0=None,
        inner: Format | None = None, u_inner=None, inner_tol=1e-3, max_outer=100,
-       check_every=10, out=None):
-    """Returns (x, info dict).  ``inner`` switches on FP64 defect correction."""
+       check_every=10, out=None, method="cg"):
+    """Returns (x, info dict).  ``inner`` switches on FP64 defect correction;
+    ``method`` "cg" (CGLS / CG) or "bicgstab" (also for the inner solves)."""
     p = W.weo_solver_params()
     p.op = OPS[op]
     p.nrhs = int(nrhs)
@@ -35,6 +39,7 @@ def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000,
     p.inner_tol = float(inner_tol)
     p.max_outer = int(max_outer)
     p.check_every = int(check_every)
+    p.method = METHODS[method]
     nbytes = W.wilson_eo_cg_workspace_bytes(lat.c, fmt.c, p)
     if nbytes == 0:
         raise W.WilsonEOError(W.WEO_ERR_ARG, "wilson_eo_cg_workspace_bytes")

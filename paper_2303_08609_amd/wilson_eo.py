@@ -26,6 +26,7 @@ WEO_F64, WEO_F32, WEO_F16, WEO_BF16 = 0, 1, 2, 3
 WEO_LINK18, WEO_LINK12 = 0, 1
 WEO_MAX_RHS = 16
 WEO_OP_M, WEO_OP_MDAGM, WEO_OP_DW = 0, 1, 2
+WEO_SOLVER_CG, WEO_SOLVER_BICGSTAB = 0, 1
 WEO_FORCE_PROJECT, WEO_FORCE_ACCUMULATE = 1, 2
 
 
@@ -40,7 +41,8 @@ class weo_format(C.Structure):
 class weo_solver_params(C.Structure):
     _fields_ = [("op", C.c_int), ("nrhs", C.c_int), ("tol", C.c_double), ("maxiter", C.c_int),
                 ("x0_given", C.c_int), ("mixed", C.c_int), ("inner", weo_format),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
+                ("method", C.c_int)]
 
 
 class weo_solver_info(C.Structure):

@@ -130,3 +130,11 @@ def test_face_sizes_and_validation_without_gpu():
     assert W.wilson_eo_face_unpack(lat, f, 1, 0, one, one, float("inf"), a, b, c, d, 1,
                                    None) == W.WEO_ERR_ARG
     assert W.wilson_eo_face_unpack(lat, f, 1, 0, one, one, 1.0, a, b, c, b, 1, None) == W.WEO_ERR_ARG
+
+
+def test_header_constants_match_the_binding():
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"^#define\s+(WEO_\w+)\s+(-?\d+)", text, flags=re.M))
+    assert len(defs) >= 10
+    for name, val in defs.items():
+        assert getattr(W, name) == int(val), name
