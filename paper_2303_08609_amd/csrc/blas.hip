@@ -344,20 +344,20 @@ struct BiArgs {
 
 __device__ __forceinline__ bool bi_live(const int* mask, int r) { return mask == nullptr || mask[r] != 0; }
 
-// partial <a, b> = sum conj(a) b, a in ACC, b in OP
-template <int ACC, int OP>
+// partial <a, b> = sum conj(a) b, a in PA (field size F.fb_acc), b in PB (F.fb_op)
+template <int PA, int PB>
 __global__ void __launch_bounds__(kBlk) k_bi_cdot(Fields F, const int* __restrict__ mask, const uint8_t* a,
                                                   const uint8_t* b, double* pre, double* pim) {
-    using CA = cx<typename AR<ACC>::R>;
-    using CO = cx<typename AR<OP>::R>;
+    using CA = cx<typename AR<PA>::R>;
+    using CO = cx<typename AR<PB>::R>;
     const int r = blockIdx.y;
     const uint32_t i = blockIdx.x * kBlk + threadIdx.x;
     double re = 0.0, im = 0.0;
     if (bi_live(mask, r) && i < F.vh) {
         CA av[12];
         CO bv[12];
-        load_rec<ACC, 12>(a + (size_t)r * F.fb_acc, F.vh, i, av);
-        load_rec<OP, 12>(b + (size_t)r * F.fb_op, F.vh, i, bv);
+        load_rec<PA, 12>(a + (size_t)r * F.fb_acc, F.vh, i, av);
+        load_rec<PB, 12>(b + (size_t)r * F.fb_op, F.vh, i, bv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             re += (double)av[k].x * (double)bv[k].x + (double)av[k].y * (double)bv[k].y;
@@ -440,6 +440,7 @@ __global__ void __launch_bounds__(kBlk) k_bi_ts(Fields F, const int* __restrict_
 }
 
 // x += alpha p + omega s;  r = s - omega t;  partials ||r||^2 and <r^, r>
+// (r^ in OP)
 template <int ACC, int OP>
 __global__ void __launch_bounds__(kBlk) k_bi_xr(Fields F, BiArgs B, uint8_t* x, const uint8_t* p,
                                                 const uint8_t* s, const uint8_t* t, uint8_t* rv,
@@ -470,8 +471,8 @@ __global__ void __launch_bounds__(kBlk) k_bi_xr(Fields F, BiArgs B, uint8_t* x, 
         }
         store_rec<ACC, 12>(xrow, F.vh, i, xv);
         store_rec<ACC, 12>(rv + (size_t)r * F.fb_acc, F.vh, i, sv);
-        CA hv[12];
-        load_rec<ACC, 12>(rh + (size_t)r * F.fb_acc, F.vh, i, hv);
+        CO hv[12];
+        load_rec<OP, 12>(rh + (size_t)r * F.fb_op, F.vh, i, hv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const double hx = hv[k].x, hy = hv[k].y, rx = sv[k].x, ry = sv[k].y;
@@ -522,7 +523,7 @@ __global__ void __launch_bounds__(kBlk) k_bi_p(Fields F, BiArgs B, const uint8_t
 }
 
 // Scalar steps, one workgroup per rhs; pa, pb, pc are [nrhs][nb] partials.
-//   BI_INIT:  pa = ||r||^2        -> rho = ||r||^2, ss = ||r||^2, alpha = omega = 1
+//   BI_INIT:  pa = ||r||^2, pb, pc = <r^, r> -> ss, rho = <r^, r>, alpha = omega = 1
 //   BI_ALPHA: pa, pb = <r^, v>     -> alpha = rho / <r^, v>
 //   BI_OMEGA: pa, pb = <t, s>, pc = ||t||^2 -> omega = <t, s> / ||t||^2 (0 if t = 0)
 //   BI_BETA:  pa = ||r||^2, pb, pc = <r^, r> -> ss, beta = (rho'/rho)(alpha/omega), rho = rho'
@@ -538,7 +539,7 @@ __global__ void __launch_bounds__(kRed) k_bi_scalars(int kind, BiArgs B, int nb,
     if (!bi_live(B.mask, r)) return;
     auto fail = [&]() { B.flags[r] |= 1; B.mask[r] = 0; };
     if (kind == BI_INIT) {
-        cset(B.rho, r, make_double2(a, 0.0));
+        cset(B.rho, r, make_double2(b, c));
         cset(B.alpha, r, make_double2(1.0, 0.0));
         cset(B.omega, r, make_double2(1.0, 0.0));
         cset(B.beta, r, make_double2(0.0, 0.0));
@@ -724,15 +725,23 @@ static BiArgs bi_args(const BiScalHost& h) {
     else if (ACCP == P_F32 && OPP == P_BF16) { constexpr int A_ = P_F32, O_ = P_BF16; CALL; } \
     else return hipErrorInvalidValue;
 
-hipError_t launch_bi_cdot(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const int* mask, const void* a,
+template <int PA>
+static hipError_t bi_cdot_b(int pb, const Fields& F, dim3 grid, const int* mask, const uint8_t* A,
+                            const uint8_t* Bv, double* pre, double* pim, hipStream_t st) {
+    const dim3 block(kBlk);
+    WEO_SP_SWITCH(pb, hipLaunchKernelGGL((k_bi_cdot<PA, SPV>), grid, block, 0, st, F, mask, A, Bv, pre, pim))
+    return hipGetLastError();
+}
+
+hipError_t launch_bi_cdot(const Geom& g, int fmt_a, int fmt_b, int nrhs, const int* mask, const void* a,
                           const void* b, double* pre, double* pim, hipStream_t st) {
-    const Fields F = fields(g, fmt_acc, fmt_op);
-    const dim3 grid(blas_blocks(g), nrhs), block(kBlk);
+    const Fields F = fields(g, fmt_a, fmt_b);
+    const dim3 grid(blas_blocks(g), nrhs);
     auto* A = static_cast<const uint8_t*>(a);
     auto* Bv = static_cast<const uint8_t*>(b);
-    WEO_BI_PAIRS(sp_of(fmt_acc), sp_of(fmt_op),
-                 hipLaunchKernelGGL((k_bi_cdot<A_, O_>), grid, block, 0, st, F, mask, A, Bv, pre, pim))
-    return hipGetLastError();
+    const int pb = sp_of(fmt_b);
+    WEO_SP_SWITCH(sp_of(fmt_a), return bi_cdot_b<SPV>(pb, F, grid, mask, A, Bv, pre, pim, st))
+    return hipSuccess;
 }
 
 hipError_t launch_bi_s(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const BiScalHost& h, const void* r,

@@ -77,7 +77,7 @@ struct Scalars {
 struct Workspace {
     // fields (nrhs each)
     void *s_acc, *x_acc, *s_op, *p, *q, *r, *t, *tmp;     // level vectors
-    void *rh, *s2;                                        // BiCGStab: shadow residual, s (acc)
+    void *rh, *s2;                                        // BiCGStab: shadow residual (op), s (acc)
     void *r64, *t64, *tmp64;                              // outer (mixed) vectors
     double *pa, *pb, *pc;                                 // partial sums
     Scalars sc;
@@ -112,7 +112,7 @@ Workspace carve_ws(const Geom& g, int fmt, const weo_solver_params* p, int inner
     w.t = c.take(fo);
     w.tmp = c.take(fo);
     if (p->method == WEO_SOLVER_BICGSTAB) {
-        w.rh = c.take(fa);
+        w.rh = c.take(fo);
         w.s2 = c.take(fa);
     }
     if (p->mixed) {
@@ -377,7 +377,8 @@ int run_level(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const
 // BiCGStab at one precision level.  Same contract as run_level: x_acc holds
 // the start, s_acc the matching residual b - A x, mask the live rhs and
 // bb[r] = ||b||^2; stops per rhs when ||r||^2 <= tol^2 bb.  Vectors: r = s_acc,
-// r^ = rh, s = s2 (all fmt_acc); p, v = q, t, s_op, mid = r (fmt_op).
+// s = s2 (fmt_acc); r^ = rh, p, v = q, t, s_op, mid = r (fmt_op).  Any fixed
+// r^ serves; keeping it in the operator's format halves its traffic.
 int run_level_bicg(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, const void* u, void* x_acc,
                    int nrhs, double tol, int maxiter, int check_every, LevelResult* res) {
     const Geom& g = c.gb;
@@ -395,11 +396,12 @@ int run_level_bicg(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, 
     std::vector<int> mask(nrhs);
     std::vector<double> bb(nrhs);
     HIPCHK(hipMemcpyAsync(bb.data(), w.sc.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
-    // r^ = r, p = r, rho = ||r||^2
-    HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_acc, w.rh, nrhs, nullptr, 0, c.st));
+    // r^ = r (rounded to fmt_op), p = r, rho = <r^, r>
+    HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_op, w.rh, nrhs, nullptr, 0, c.st));
     HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_op, w.p, nrhs, nullptr, 0, c.st));
     HIPCHK(launch_norm2(g, fmt_acc, w.s_acc, nrhs, w.pa, c.st));
-    HIPCHK(launch_bi_scalars(BI_INIT, B, nbb, w.pa, nullptr, nullptr, c.st));
+    HIPCHK(launch_bi_cdot(g, fmt_op, fmt_acc, nrhs, w.sc.mask, w.rh, w.s_acc, w.pb, w.pc, c.st));
+    HIPCHK(launch_bi_scalars(BI_INIT, B, nbb, w.pa, w.pb, w.pc, c.st));
     int live = look_at(c, w, nrhs, tol2, bb, ss, mask, res);
     if (live < 0) return live;
     if (!live) return WEO_OK;
@@ -407,7 +409,7 @@ int run_level_bicg(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, 
     int look = plan.first();
     for (int it = 1; it <= maxiter; ++it) {
         HIPCHK(apply_op(c, op, fmt_op, u, w.p, w.q, w.r, w.tmp, nrhs, nullptr));
-        HIPCHK(launch_bi_cdot(g, fmt_acc, fmt_op, nrhs, w.sc.mask, w.rh, w.q, w.pa, w.pb, c.st));
+        HIPCHK(launch_bi_cdot(g, fmt_op, fmt_op, nrhs, w.sc.mask, w.rh, w.q, w.pa, w.pb, c.st));
         HIPCHK(launch_bi_scalars(BI_ALPHA, B, nbb, w.pa, w.pb, nullptr, c.st));
         HIPCHK(launch_bi_s(g, fmt_acc, fmt_op, nrhs, B, w.s_acc, w.q, w.s2, s_op, w.pc, c.st));
         HIPCHK(apply_op(c, op, fmt_op, u, s_op, w.t, w.r, w.tmp, nrhs, nullptr));

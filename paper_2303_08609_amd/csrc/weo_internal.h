@@ -122,7 +122,7 @@ hipError_t launch_scalars(int kind, const ScalarArgsHost& a, hipStream_t s);
 
 // ---- BiCGStab vector and scalar steps ---------------------------------------
 // Complex per-rhs scalars are (re, im) pairs of doubles in device memory.
-// x, r, r^, s in fmt_acc; p, v, t, s_op in fmt_op (s_op written only when
+// x, r, s in fmt_acc; r^, p, v, t, s_op in fmt_op (s_op written only when
 // the two formats store spinors differently).  Partials are [nrhs][blas_blocks].
 enum { BI_INIT = 0, BI_ALPHA = 1, BI_OMEGA = 2, BI_BETA = 3 };
 struct BiScalHost {
@@ -137,8 +137,8 @@ struct BiScalHost {
     int* mask;
     int* flags;
 };
-// partials of <a, b> (a in fmt_acc, b in fmt_op)
-hipError_t launch_bi_cdot(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const int* mask, const void* a,
+// partials of <a, b> (a in fmt_a, b in fmt_b)
+hipError_t launch_bi_cdot(const Geom& g, int fmt_a, int fmt_b, int nrhs, const int* mask, const void* a,
                           const void* b, double* pre, double* pim, hipStream_t st);
 // s = r - alpha v, s_op = s, partial ||s||^2
 hipError_t launch_bi_s(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const BiScalHost& h, const void* r,

@@ -59,8 +59,8 @@ def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000,
 
 
 def bench_solves(lat: Lattice, u_np, psi_np, u_dev64, psi_dev64, reps=1):
-    """Solve M x = b on the benchmark lattice:
-    * plain FP32 CGLS to 1e-6 (its recursive-residual target; true residual
+    """Solve M x = b on the benchmark lattice, by CGLS and by BiCGStab:
+    * plain FP32 to 1e-6 (the recursive-residual target; true residual
       reported);
     * FP64 defect correction to 1e-10 with FP32 inner solves (the plain-FP32
       path at 1e-10: pure FP32 cannot reach it);
@@ -88,25 +88,31 @@ def bench_solves(lat: Lattice, u_np, psi_np, u_dev64, psi_dev64, reps=1):
                 best = (dt, info)
         return best
 
-    dt, info = timed(lambda: cg(lat, f32, u32, b32, tol=1e-6, maxiter=20000))
-    out["fp32_cgls_1e-6"] = {"seconds": round(dt, 4), "iters": info["iters"],
-                             "true_rel_resid_fp32": info["true_rel_resid"][0],
-                             "status": info["status"]}
+    for meth, tag in (("cg", "cgls"), ("bicgstab", "bicgstab")):
+        timed(lambda: cg(lat, f32, u32, b32, tol=1e-6, maxiter=20000, method=meth))   # untimed
+        dt, info = timed(lambda: cg(lat, f32, u32, b32, tol=1e-6, maxiter=20000, method=meth))
+        out[f"fp32_{tag}_1e-6"] = {"seconds": round(dt, 4), "iters": info["iters"],
+                                   "applies": info["applies"],
+                                   "true_rel_resid_fp32": info["true_rel_resid"][0],
+                                   "status": info["status"]}
     inners = {"fp32": Format("f32", "f32", 18), "bf16_f16link12": Format("bf16", "f16", 12),
               "f16_f16link12": Format("f16", "f16", 12)}
     for name, inner in inners.items():
         ui = lat.pack_gauge(u_dev64, inner)
-        dt, info = timed(lambda: cg(lat, f64, u64, b64, tol=1e-10, maxiter=50000, inner=inner,
-                                    u_inner=ui, inner_tol=1e-3 if name != "fp32" else 1e-5,
-                                    max_outer=100))
-        out[f"dc_{name}_1e-10"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
-                                   "outer_iters": info["outer_iters"],
-                                   "true_rel_resid_fp64": info["true_rel_resid"][0],
-                                   "status": info["status"]}
+        for meth, tag in (("cg", ""), ("bicgstab", "_bicgstab")):
+            dt, info = timed(lambda: cg(lat, f64, u64, b64, tol=1e-10, maxiter=50000, inner=inner,
+                                        u_inner=ui, inner_tol=1e-3 if name != "fp32" else 1e-5,
+                                        max_outer=100, method=meth))
+            out[f"dc_{name}{tag}_1e-10"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
+                                            "outer_iters": info["outer_iters"],
+                                            "applies": info["applies"],
+                                            "true_rel_resid_fp64": info["true_rel_resid"][0],
+                                            "status": info["status"]}
         del ui
     base = out["dc_fp32_1e-10"]["seconds"]
-    for k in ("dc_bf16_f16link12_1e-10", "dc_f16_f16link12_1e-10"):
-        out[k]["speedup_vs_fp32_inner"] = round(base / out[k]["seconds"], 3)
+    for k in list(out):
+        if k.startswith("dc_") and k != "dc_fp32_1e-10":
+            out[k]["speedup_vs_fp32_inner_cgls"] = round(base / out[k]["seconds"], 3)
     out["full_system_fp32_1e-6"] = eo_vs_dw(lat, u32, b32, psi_odd_seed=203)
     return out
 
@@ -157,7 +163,8 @@ def bench_solves_12rhs(dims=(32, 32, 32, 64), kappa=0.126, eps=0.5, seed_gauge=4
       solves, one right-hand side after the other;
     * batched mixed path: the 12 sources in one solve, FP64 defect correction
       around batched inner solves with FP16 / BF16 spinors and FP16 12-real
-      links (inner tolerance 1e-3).
+      links (inner tolerance 1e-3);
+    each by CGLS and by BiCGStab inner solves.
     Links are packed before timing; each timed path runs once untimed first
     (kernel loading, multi-rhs shape tuning)."""
     from . import inputs
@@ -187,26 +194,39 @@ def bench_solves_12rhs(dims=(32, 32, 32, 64), kappa=0.126, eps=0.5, seed_gauge=4
         iters += info["iters"]
     out["fp32_inner_sequential"] = {"seconds": round(total, 4), "inner_iters": iters,
                                     "worst_true_rel_resid": worst}
+    # the same one source at a time with FP32 inner BiCGStab
+    total, worst, iters = 0.0, 0.0, 0
+    for r in range(12):
+        br = b64[r * fsize:(r + 1) * fsize]
+        dt, (x, info) = _timed(lambda: cg(lat, f64, u64, br, tol=1e-10, inner=f32, u_inner=u32,
+                                          inner_tol=1e-5, maxiter=50000, max_outer=100,
+                                          method="bicgstab"))
+        total += dt
+        worst = max(worst, info["true_rel_resid"][0])
+        iters += info["iters"]
+    out["fp32_inner_sequential_bicgstab"] = {"seconds": round(total, 4), "inner_iters": iters,
+                                             "worst_true_rel_resid": worst}
     del u32
     for name, inner in (("f16_f16link12", Format("f16", "f16", 12)),
                         ("bf16_f16link12", Format("bf16", "f16", 12)),
                         ("fp32", Format("f32", "f32", 18))):
         ui = lat.pack_gauge(ud, inner)
         tol_in = 1e-5 if name == "fp32" else 1e-3
-        cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=inner, u_inner=ui, inner_tol=tol_in,
-           maxiter=50000, max_outer=100)                   # first call tunes the hop shapes
-        dt, (x, info) = _timed(lambda: cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=inner,
-                                          u_inner=ui, inner_tol=tol_in, maxiter=50000,
-                                          max_outer=100))
-        out[f"batched12_{name}"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
-                                    "outer_iters": info["outer_iters"],
-                                    "worst_true_rel_resid": max(info["true_rel_resid"]),
-                                    "status": info["status"]}
+        for meth, tag in (("cg", ""), ("bicgstab", "_bicgstab")):
+            cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=inner, u_inner=ui, inner_tol=tol_in,
+               maxiter=50000, max_outer=100, method=meth)      # first call tunes the hop shapes
+            dt, (x, info) = _timed(lambda: cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=inner,
+                                              u_inner=ui, inner_tol=tol_in, maxiter=50000,
+                                              max_outer=100, method=meth))
+            out[f"batched12_{name}{tag}"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
+                                             "outer_iters": info["outer_iters"],
+                                             "worst_true_rel_resid": max(info["true_rel_resid"][:12]),
+                                             "status": info["status"]}
         del ui
     base = out["fp32_inner_sequential"]["seconds"]
     for k in list(out):
-        if k.startswith("batched12"):
-            out[k]["speedup_vs_fp32_sequential"] = round(base / out[k]["seconds"], 3)
+        if k.startswith("batched12") or k == "fp32_inner_sequential_bicgstab":
+            out[k]["speedup_vs_fp32_sequential_cgls"] = round(base / out[k]["seconds"], 3)
     return out
 
 
@@ -214,7 +234,7 @@ def bench_solves_large(dims=(48, 48, 48, 96), kappa=0.1265, eps=0.7, seed_gauge=
     """One Gaussian source on 48^3x96 to a true FP64 residual of 1e-10: FP64
     defect correction around FP16 / BF16 spinor + FP16 12-real link inner
     solves (inner tolerance 1e-3), against the same driver with FP32 inner
-    solves."""
+    solves; CGLS and BiCGStab inner solves."""
     from . import inputs
     lat = Lattice(dims, kappa, (1, 1, 1, -1))
     u = inputs.gen_gauge(dims, eps, seed_gauge)
@@ -229,13 +249,16 @@ def bench_solves_large(dims=(48, 48, 48, 96), kappa=0.1265, eps=0.7, seed_gauge=
                         ("bf16_f16link12", Format("bf16", "f16", 12))):
         ui = lat.pack_gauge(ud, inner)
         tol_in = 1e-5 if name == "fp32" else 1e-3
-        dt, (x, info) = _timed(lambda: cg(lat, f64, u64, b64, tol=1e-10, inner=inner, u_inner=ui,
-                                          inner_tol=tol_in, maxiter=50000, max_outer=100))
-        out[f"dc_{name}"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
-                             "outer_iters": info["outer_iters"],
-                             "true_rel_resid_fp64": info["true_rel_resid"][0], "status": info["status"]}
+        for meth, tag in (("cg", ""), ("bicgstab", "_bicgstab")):
+            dt, (x, info) = _timed(lambda: cg(lat, f64, u64, b64, tol=1e-10, inner=inner, u_inner=ui,
+                                              inner_tol=tol_in, maxiter=50000, max_outer=100, method=meth))
+            out[f"dc_{name}{tag}"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
+                                      "outer_iters": info["outer_iters"],
+                                      "true_rel_resid_fp64": info["true_rel_resid"][0],
+                                      "status": info["status"]}
         del ui
     base = out["dc_fp32"]["seconds"]
-    for k in ("dc_f16_f16link12", "dc_bf16_f16link12"):
-        out[k]["speedup_vs_fp32_inner"] = round(base / out[k]["seconds"], 3)
+    for k in list(out):
+        if k != "dc_fp32":
+            out[k]["speedup_vs_fp32_inner_cgls"] = round(base / out[k]["seconds"], 3)
     return out
