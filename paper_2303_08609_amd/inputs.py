@@ -209,6 +209,17 @@ def gen_spinor_full(dims, seed: int) -> np.ndarray:
     return _complex_normal(rng(seed), (lt, lz, ly, lx, 4, 3))
 
 
+def gen_site_blocks(dims, eps: float, seed: int) -> np.ndarray:
+    """Site-local diagonal blocks of a clover-type operator: per site two 6 x 6
+    Hermitian matrices 1 + eps * X, X with Gaussian entries (X = (G + G^dag) / 2
+    scaled by 6^-1/2), complex128 [Lt][Lz][Ly][Lx][2][6][6].  Near the identity
+    (invertible for eps well below 1), like 1 + c sigma.F on smooth links."""
+    lx, ly, lz, lt = check_dims(dims)
+    g = _complex_normal(rng(seed), (lt, lz, ly, lx, 2, 6, 6))
+    x = 0.5 * (g + np.conj(np.swapaxes(g, -1, -2))) / np.sqrt(6.0)
+    return np.eye(6, dtype=np.complex128) + eps * x
+
+
 def gen_point_noise_sources(dims, seed: int, sigma: float | None = None) -> np.ndarray:
     """12 sources (one per spin x colour) on the even sublattice.
 
