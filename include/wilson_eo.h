@@ -214,6 +214,51 @@ int wilson_eo_face_unpack(const weo_lattice* lat, const weo_format* fmt,
                           const void* u, const void* recv_lo, const void* recv_hi,
                           void* out, int nrhs, void* stream);
 
+/* ---- site-local diagonal blocks (clover-type D_ee, D_oo; Sec. 2) ----------
+ * For the clover matrix D_ee and D_oo are site-local block-diagonal
+ * operations (Sec. 2).  Here D = A - kappa H with A(x) a 12 x 12 Hermitian
+ * site matrix commuting with gamma5 (as 1 + c sigma_mu_nu F_mu_nu does), so
+ * that D_eo = -kappa H_eo, D_oe = -kappa H_oe and A is given by two 6 x 6
+ * Hermitian blocks in the gamma5 eigenbasis (gamma5 = -[[0,1],[1,0]] in 2 x 2
+ * spin blocks of the Dirac representation):
+ *     psi_A = (psi_{s} + psi_{s+2}) / sqrt2,  s = 0, 1   -> block 0 (gamma5 = -1)
+ *     psi_B = (psi_{s} - psi_{s+2}) / sqrt2               -> block 1 (gamma5 = +1)
+ * each 6-vector ordered k = 3 s + colour.
+ * Canonical layout (complex128 / complex64, full lattice):
+ *     blocks [Lt][Lz][Ly][Lx][2][6][6]     B_b(x)_{k,l}
+ * Only the lower triangle and the real parts of the diagonal are read (the
+ * blocks are Hermitian).  Packed: both parities, in the link precision.
+ * With invert = 1 the packed blocks are the inverses (FP64 Gauss-Jordan with
+ * partial pivoting on the GPU; a singular block gives non-finite entries). */
+size_t weo_clover_bytes(const weo_lattice* lat, const weo_format* fmt);
+int weo_pack_clover(const weo_lattice* lat, const weo_format* fmt, const void* canon, int canon_prec,
+                    int invert, void* packed, void* stream);
+
+/* out = y + alpha C_p in  (y == NULL: out = C_p in) for nrhs spinors of parity
+ * `parity`, C the packed blocks (A or A^-1 as packed).  y may be out; in must
+ * not overlap out. */
+int wilson_eo_clover_site(const weo_lattice* lat, const weo_format* fmt, int parity,
+                          const void* clover, const void* in, const void* y, double alpha,
+                          void* out, int nrhs, void* stream);
+
+/* Hop followed by the output parity's blocks:
+ *   out = C_p P_p H P_{1-p} in           (y == NULL)
+ *   out = y + alpha C_p P_p H P_{1-p} in (H^dag with dagger = 1)
+ * With inverse blocks and alpha = kappa this gives Eq. (5),
+ * xi_o = A_oo^-1 eta_o + kappa A_oo^-1 H_oe xi_e (y = A_oo^-1 eta_o), and the
+ * right-hand side of Eq. (4).  y may be out; in must not overlap out. */
+int wilson_eo_clover_hop(const weo_lattice* lat, const weo_format* fmt, int out_parity, int dagger,
+                         const void* u, const void* clover, const void* in, const void* y,
+                         double alpha, void* out, int nrhs, void* stream);
+
+/* Eq. (4), left-hand side, with site blocks (clover_inv = packed A^-1):
+ *   out = M in = in - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe in   (dagger = 0)
+ *   out = M^dag in = in - kappa^2 H_eo^dag A_oo^-1 H_oe^dag A_ee^-1 in  (dagger = 1)
+ * tmp: nrhs odd-parity spinors of scratch. */
+int wilson_eo_clover_apply(const weo_lattice* lat, const weo_format* fmt, int dagger,
+                           const void* u, const void* clover_inv, const void* in, void* out,
+                           void* tmp, int nrhs, void* stream);
+
 /* The even-odd operator of Eq. (4), left-hand side, on the even sublattice:
  *   out = M in = in - kappa^2 H_eo H_oe in   (dagger = 0)
  *   out = M^dag in                           (dagger = 1)
@@ -251,6 +296,12 @@ typedef struct {
     int        check_every; /* iterations between host convergence checks (>=1) */
     int        method;      /* WEO_SOLVER_CG or WEO_SOLVER_BICGSTAB (also for the
                                inner solves of defect correction) */
+    const void* clover;     /* NULL: Wilson (D_ee = D_oo = 1).  Else packed INVERSE
+                               site blocks (weo_pack_clover, invert = 1) in format
+                               fmt: the operator is the clover-type M of
+                               wilson_eo_clover_apply.  Not with WEO_OP_DW. */
+    const void* clover_inner; /* the same blocks packed in format `inner` (mixed
+                               only; required with clover) */
 } weo_solver_params;
 
 typedef struct {

@@ -307,6 +307,106 @@ int wilson_eo_hop_axpy(const weo_lattice* lat, const weo_format* fmt, int out_pa
     return hip_status(launch_hop(h, static_cast<hipStream_t>(stream)));
 }
 
+size_t weo_clover_bytes(const weo_lattice* lat, const weo_format* fmt) {
+    Geom g;
+    int id;
+    if (check_lattice(lat, &g) != WEO_OK || check_fmt(fmt, &id) != WEO_OK) return 0;
+    return clover_field_bytes(g, id);
+}
+
+int weo_pack_clover(const weo_lattice* lat, const weo_format* fmt, const void* canon, int canon_prec, int invert,
+                    void* packed, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if (canon_prec != WEO_F64 && canon_prec != WEO_F32) return WEO_ERR_ARG;
+    if (invert != 0 && invert != 1) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(canon));
+    WEO_TRY(check_ptr(packed));
+    const size_t nc = (size_t)g.vh * 2 * 2 * 36 * (canon_prec == WEO_F64 ? 16 : 8);
+    if (overlaps(canon, nc, packed, clover_field_bytes(g, id))) return WEO_ERR_ARG;
+    return hip_status(launch_pack_clover(g, id, canon, canon_prec == WEO_F64, invert, packed,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+int wilson_eo_clover_site(const weo_lattice* lat, const weo_format* fmt, int parity, const void* clover,
+                          const void* in, const void* y, double alpha, void* out, int nrhs, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if ((parity != 0 && parity != 1) || nrhs < 1 || nrhs > WEO_MAX_RHS || !std::isfinite(alpha))
+        return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(clover));
+    WEO_TRY(check_ptr(in));
+    WEO_TRY(check_ptr(out));
+    if (y) WEO_TRY(check_ptr(y));
+    const size_t sb = (size_t)nrhs * spinor_field_bytes(g, id);
+    if (overlaps(in, sb, out, sb) || overlaps(clover, clover_field_bytes(g, id), out, sb)) return WEO_ERR_ARG;
+    return hip_status(launch_clover_site(g, id, parity, clover, in, y, alpha, out, nrhs,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+int wilson_eo_clover_hop(const weo_lattice* lat, const weo_format* fmt, int out_parity, int dagger,
+                         const void* u, const void* clover, const void* in, const void* y, double alpha,
+                         void* out, int nrhs, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if ((out_parity != 0 && out_parity != 1) || (dagger != 0 && dagger != 1)) return WEO_ERR_ARG;
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS || !std::isfinite(alpha)) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(u));
+    WEO_TRY(check_ptr(clover));
+    WEO_TRY(check_ptr(in));
+    WEO_TRY(check_ptr(out));
+    if (y) WEO_TRY(check_ptr(y));
+    const size_t sb = (size_t)nrhs * spinor_field_bytes(g, id);
+    if (overlaps(in, sb, out, sb) || overlaps(u, gauge_field_bytes(g, id), out, sb) ||
+        overlaps(clover, clover_field_bytes(g, id), out, sb))
+        return WEO_ERR_ARG;
+    HopLaunch h;
+    h.g = g;
+    h.fmt = id;
+    h.out_par = out_parity;
+    h.dagger = dagger;
+    phases_of(lat, h.phase);
+    h.u = u;
+    h.in = in;
+    h.out = out;
+    h.y = y;
+    h.alpha = y ? alpha : 0.0;
+    h.partial = nullptr;
+    h.nrhs = nrhs;
+    return hip_status(launch_hop_clover(h, clover, static_cast<hipStream_t>(stream)));
+}
+
+int wilson_eo_clover_apply(const weo_lattice* lat, const weo_format* fmt, int dagger, const void* u,
+                           const void* clover_inv, const void* in, void* out, void* tmp, int nrhs, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(check_lattice(lat, &g));
+    WEO_TRY(check_fmt(fmt, &id));
+    if (dagger != 0 && dagger != 1) return WEO_ERR_ARG;
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(u));
+    WEO_TRY(check_ptr(clover_inv));
+    WEO_TRY(check_ptr(in));
+    WEO_TRY(check_ptr(out));
+    WEO_TRY(check_ptr(tmp));
+    const size_t sb = (size_t)nrhs * spinor_field_bytes(g, id);
+    const size_t gb = gauge_field_bytes(g, id), cb = clover_field_bytes(g, id);
+    if (overlaps(in, sb, out, sb) || overlaps(in, sb, tmp, sb) || overlaps(out, sb, tmp, sb) ||
+        overlaps(u, gb, out, sb) || overlaps(u, gb, tmp, sb) || overlaps(clover_inv, cb, out, sb) ||
+        overlaps(clover_inv, cb, tmp, sb))
+        return WEO_ERR_ARG;
+    double ph[4][2];
+    phases_of(lat, ph);
+    return hip_status(launch_apply_clover(g, id, ph, lat->kappa, dagger, u, clover_inv, in, out, tmp, nrhs,
+                                          nullptr, static_cast<hipStream_t>(stream)));
+}
+
 int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger, const void* u,
                     const void* in, void* out, void* tmp, int nrhs, void* stream) {
     Geom g;

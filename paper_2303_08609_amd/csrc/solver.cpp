@@ -21,6 +21,8 @@
 //     v = A p;  alpha = rho / <r^, v>;  s = r - alpha v;  t = A s;
 //     omega = <t, s> / ||t||^2;  x += alpha p + omega s;  r = s - omega t;
 //     rho' = <r^, r>;  beta = (rho' / rho)(alpha / omega);  p = r + beta (p - omega v)
+//  With site blocks (clover-type D_ee, D_oo; packed inverse blocks C) the
+//  operator is M = 1 - kappa^2 C_e H_eo C_o H_oe of Eq. (4), same solvers.
 //  Defect correction (mixed precision): in FP64, r = b - A x; the residual is
 //  rescaled to unit RMS component, solved approximately in the inner format
 //  (relative tolerance inner_tol) and the correction added back in FP64.
@@ -143,6 +145,7 @@ struct Ctx {
     Geom gb;                // vector geometry: g, or twice the sites for full fields
     bool full;              // operator on full (both-parity) fields
     uint32_t nb_apply;      // norm partials per rhs written by an operator apply
+    const void* clv;        // packed inverse site blocks of the current level (clover-type M) or null
     double ph[4][2];
     hipStream_t st;
     int applies;
@@ -151,6 +154,11 @@ struct Ctx {
 // out = A in with A = M (dagger 0) or M^dag (dagger 1); partial = ||out||^2.
 hipError_t apply_m(Ctx& c, int fmt, const void* u, int dagger, const void* in, void* out, void* tmp,
                    int nrhs, double* partial) {
+    if (c.clv) {
+        ++c.applies;
+        return launch_apply_clover(c.g, fmt, c.ph, c.lat->kappa, dagger, u, c.clv, in, out, tmp, nrhs, partial,
+                                   c.st);
+    }
     HopLaunch h;
     h.g = c.g;
     h.fmt = fmt;
@@ -478,6 +486,9 @@ int check_params(const weo_solver_params* p, int fmt, int* inner_fmt) {
     if (p->check_every < 1 || (p->x0_given != 0 && p->x0_given != 1)) return WEO_ERR_ARG;
     if (p->mixed != 0 && p->mixed != 1) return WEO_ERR_ARG;
     if (p->method != WEO_SOLVER_CG && p->method != WEO_SOLVER_BICGSTAB) return WEO_ERR_ARG;
+    // site blocks: the even-odd operator only; the inner level needs its own
+    if ((p->clover || p->clover_inner) && p->op == WEO_OP_DW) return WEO_ERR_ARG;
+    if (p->mixed && (p->clover != nullptr) != (p->clover_inner != nullptr)) return WEO_ERR_ARG;
     *inner_fmt = fmt;
     if (p->mixed) {
         if (fmt_info(fmt).spinor_prec != WEO_F64) return WEO_ERR_FORMAT;
@@ -524,6 +535,8 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
     if ((rc = check_ptr(u)) != WEO_OK || (rc = check_ptr(b)) != WEO_OK || (rc = check_ptr(x)) != WEO_OK)
         return rc;
     if (p->mixed && (rc = check_ptr(u_inner)) != WEO_OK) return rc;
+    if (p->clover && (rc = check_ptr(p->clover)) != WEO_OK) return rc;
+    if (p->mixed && p->clover_inner && (rc = check_ptr(p->clover_inner)) != WEO_OK) return rc;
     if ((rc = check_ptr(workspace)) != WEO_OK) return rc == WEO_ERR_ARG ? WEO_ERR_WORKSPACE : rc;
     const Geom gb = vector_geom(g, p->op);
     if ((uint64_t)gb.vh > (1ull << 26)) return WEO_ERR_DIMS;
@@ -542,6 +555,7 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
     c.gb = gb;
     c.full = p->op == WEO_OP_DW;
     c.nb_apply = c.full ? blas_blocks(gb) : hop_partials(g);
+    c.clv = p->clover;
     phases_of(lat, c.ph);
     c.st = static_cast<hipStream_t>(stream);
     c.applies = 0;
@@ -606,9 +620,11 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             HIPCHK(hipMemcpyAsync(w.sc.bb, tg.data(), n * sizeof(double), hipMemcpyHostToDevice, c.st));
             if ((rc = set_mask(c, w, live)) != WEO_OK) return rc;
             LevelResult lr;
-            if ((rc = run_method(c, w, p->method, p->op, inner, kAccF32, u_inner, w.x_acc, n, p->inner_tol,
-                                 p->maxiter - inner_iters, p->check_every, &lr)) != WEO_OK)
-                return rc;
+            c.clv = p->clover_inner;
+            rc = run_method(c, w, p->method, p->op, inner, kAccF32, u_inner, w.x_acc, n, p->inner_tol,
+                            p->maxiter - inner_iters, p->check_every, &lr);
+            c.clv = p->clover;
+            if (rc != WEO_OK) return rc;
             inner_iters += lr.iters;
             breakdown = breakdown || lr.breakdown;
             // x += x_acc * sc_out (only live rhs changed: x_acc = 0 elsewhere)

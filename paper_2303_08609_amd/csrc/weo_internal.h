@@ -172,6 +172,23 @@ hipError_t launch_face_unpack(const Geom& g, int fmt, int out_par, int dagger, c
                               const double ph_hi[2], double alpha, const void* u, const void* lo,
                               const void* hi, void* out, int nrhs, hipStream_t s);
 
+// ---- clover-type site blocks (layout in clover_core.h) -------------------------
+size_t clover_block_bytes(const Geom& g, int fmt);   // one (parity, block) field
+size_t clover_field_bytes(const Geom& g, int fmt);   // both parities, both blocks
+// canonical blocks [Lt][Lz][Ly][Lx][2][6][6] -> packed (inverted in FP64 if invert)
+hipError_t launch_pack_clover(const Geom& g, int fmt, const void* canon, int canon_f64, int invert, void* packed,
+                              hipStream_t s);
+// out = y + alpha C_parity in  (y == nullptr: out = C_parity in)
+hipError_t launch_clover_site(const Geom& g, int fmt, int parity, const void* clv, const void* in, const void* y,
+                              double alpha, void* out, int nrhs, hipStream_t s);
+// hop whose result is multiplied by the output parity's blocks before the
+// axpy / norm epilogue (one lane per site, nrhs grid rows)
+hipError_t launch_hop_clover(const HopLaunch& h, const void* clv, hipStream_t s);
+// M = 1 - kappa^2 C_e H_eo C_o H_oe or its adjoint (C: packed inverse blocks)
+hipError_t launch_apply_clover(const Geom& g, int fmt, const double phase[4][2], double kappa, int dagger,
+                               const void* u, const void* clv, const void* in, void* out, void* tmp, int nrhs,
+                               double* partial, hipStream_t s);
+
 // ---- force ------------------------------------------------------------------
 hipError_t launch_force(const Geom& g, int fmt, const double phase[4][2], const void* u,
                         const void* lam_e, const void* lam_o, const void* r_e,

@@ -162,6 +162,47 @@ class Lattice:
                                         int(nrhs), _stream()), "wilson_eo_face_unpack")
         return out
 
+    # ---- clover-type site blocks ---------------------------------------------
+    def clover_bytes(self, fmt: Format) -> int:
+        n = W.weo_clover_bytes(self.c, fmt.c)
+        if n == 0:
+            raise W.WilsonEOError(W.WEO_ERR_ARG, "weo_clover_bytes")
+        return n
+
+    def pack_clover(self, blocks_canon: torch.Tensor, fmt: Format, invert=True, out=None):
+        """Canonical blocks [Lt][Lz][Ly][Lx][2][6][6] -> packed (inverse if invert)."""
+        lx, ly, lz, lt = self.dims
+        if tuple(blocks_canon.shape) != (lt, lz, ly, lx, 2, 6, 6):
+            raise ValueError(f"block shape {tuple(blocks_canon.shape)}")
+        out = torch.empty(self.clover_bytes(fmt), dtype=torch.uint8, device=blocks_canon.device) \
+            if out is None else out
+        W.check(W.weo_pack_clover(self.c, fmt.c, _ptr(blocks_canon), _canon_prec(blocks_canon),
+                                  int(bool(invert)), _ptr(out), _stream()), "weo_pack_clover")
+        return out
+
+    def clover_site(self, clv, x, fmt: Format, parity, y=None, alpha=1.0, nrhs=1, out=None):
+        """out = y + alpha C_parity x (y None: out = C_parity x)."""
+        out = self.new_spinor(fmt, nrhs) if out is None else out
+        W.check(W.wilson_eo_clover_site(self.c, fmt.c, int(parity), _ptr(clv), _ptr(x), _ptr(y), float(alpha),
+                                        _ptr(out), int(nrhs), _stream()), "wilson_eo_clover_site")
+        return out
+
+    def clover_hop(self, u, clv, x, fmt: Format, out_parity, dagger=False, y=None, alpha=1.0, nrhs=1,
+                   out=None):
+        """out = C_p hop(x) (y None) or y + alpha C_p hop(x)."""
+        out = self.new_spinor(fmt, nrhs) if out is None else out
+        W.check(W.wilson_eo_clover_hop(self.c, fmt.c, int(out_parity), int(bool(dagger)), _ptr(u), _ptr(clv),
+                                       _ptr(x), _ptr(y), float(alpha), _ptr(out), int(nrhs), _stream()),
+                "wilson_eo_clover_hop")
+        return out
+
+    def clover_apply(self, u, clv_inv, x, fmt: Format, dagger=False, nrhs=1, out=None, tmp=None):
+        out = self.new_spinor(fmt, nrhs) if out is None else out
+        tmp = self.new_spinor(fmt, nrhs) if tmp is None else tmp
+        W.check(W.wilson_eo_clover_apply(self.c, fmt.c, int(bool(dagger)), _ptr(u), _ptr(clv_inv), _ptr(x),
+                                         _ptr(out), _ptr(tmp), int(nrhs), _stream()), "wilson_eo_clover_apply")
+        return out
+
     def apply(self, u, x, fmt: Format, dagger=False, nrhs=1, out=None, tmp=None):
         out = self.new_spinor(fmt, nrhs) if out is None else out
         tmp = self.new_spinor(fmt, nrhs) if tmp is None else tmp

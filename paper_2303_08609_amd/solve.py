@@ -24,9 +24,10 @@ METHODS = {"cg": W.WEO_SOLVER_CG, "bicgstab": W.WEO_SOLVER_BICGSTAB}
 
 def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000, x0=None,
        inner: Format | None = None, u_inner=None, inner_tol=1e-3, max_outer=100,
-       check_every=10, out=None, method="cg"):
+       check_every=10, out=None, method="cg", clover=None, clover_inner=None):
     """Returns (x, info dict).  ``inner`` switches on FP64 defect correction;
-    ``method`` "cg" (CGLS / CG) or "bicgstab" (also for the inner solves)."""
+    ``method`` "cg" (CGLS / CG) or "bicgstab" (also for the inner solves);
+    ``clover`` / ``clover_inner``: packed inverse site blocks (clover-type M)."""
     p = W.weo_solver_params()
     p.op = OPS[op]
     p.nrhs = int(nrhs)
@@ -40,6 +41,8 @@ def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000,
     p.max_outer = int(max_outer)
     p.check_every = int(check_every)
     p.method = METHODS[method]
+    p.clover = _ptr(clover)
+    p.clover_inner = _ptr(clover_inner)
     nbytes = W.wilson_eo_cg_workspace_bytes(lat.c, fmt.c, p)
     if nbytes == 0:
         raise W.WilsonEOError(W.WEO_ERR_ARG, "wilson_eo_cg_workspace_bytes")

@@ -42,7 +42,7 @@ class weo_solver_params(C.Structure):
     _fields_ = [("op", C.c_int), ("nrhs", C.c_int), ("tol", C.c_double), ("maxiter", C.c_int),
                 ("x0_given", C.c_int), ("mixed", C.c_int), ("inner", weo_format),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
-                ("method", C.c_int)]
+                ("method", C.c_int), ("clover", C.c_void_p), ("clover_inner", C.c_void_p)]
 
 
 class weo_solver_info(C.Structure):
@@ -76,6 +76,14 @@ _SIGS = {
     "wilson_eo_face_unpack": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int,
                                         _P(C.c_double), _P(C.c_double), C.c_double, _vp, _vp, _vp,
                                         _vp, C.c_int, _vp]),
+    "weo_clover_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format)]),
+    "weo_pack_clover": (C.c_int, [_P(weo_lattice), _P(weo_format), _vp, C.c_int, C.c_int, _vp, _vp]),
+    "wilson_eo_clover_site": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, _vp, _vp, _vp, C.c_double,
+                                        _vp, C.c_int, _vp]),
+    "wilson_eo_clover_hop": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int, _vp, _vp, _vp, _vp,
+                                       C.c_double, _vp, C.c_int, _vp]),
+    "wilson_eo_clover_apply": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, _vp, _vp, _vp, _vp, _vp,
+                                         C.c_int, _vp]),
     "wilson_eo_apply": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, _vp, _vp, _vp,
                                   _vp, C.c_int, _vp]),
     "wilson_eo_cg_workspace_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format),
@@ -151,6 +159,11 @@ weo_unpack_spinor = _call("weo_unpack_spinor")
 wilson_eo_hop = _call("wilson_eo_hop")
 wilson_eo_hop_axpy = _call("wilson_eo_hop_axpy")
 wilson_eo_apply = _call("wilson_eo_apply")
+weo_clover_bytes = _call("weo_clover_bytes")
+weo_pack_clover = _call("weo_pack_clover")
+wilson_eo_clover_site = _call("wilson_eo_clover_site")
+wilson_eo_clover_hop = _call("wilson_eo_clover_hop")
+wilson_eo_clover_apply = _call("wilson_eo_clover_apply")
 weo_face_bytes = _call("weo_face_bytes")
 wilson_eo_face_pack = _call("wilson_eo_face_pack")
 wilson_eo_face_unpack = _call("wilson_eo_face_unpack")

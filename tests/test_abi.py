@@ -138,3 +138,23 @@ def test_header_constants_match_the_binding():
     assert len(defs) >= 10
     for name, val in defs.items():
         assert getattr(W, name) == int(val), name
+
+
+def test_clover_sizes_and_validation_without_gpu():
+    lat = W.make_lattice((8, 8, 8, 8), 0.126)
+    vh = 8 ** 4 // 2
+    for (sp, lp, lf), cb in (((W.WEO_F64, W.WEO_F64, W.WEO_LINK18), 16), ((W.WEO_F32, W.WEO_F32, W.WEO_LINK12), 8),
+                             ((W.WEO_BF16, W.WEO_F16, W.WEO_LINK12), 4)):
+        # both parities, two blocks of 18 complex (real diagonal in pairs + lower triangle)
+        assert W.weo_clover_bytes(lat, W.make_format(sp, lp, lf)) == 2 * 2 * vh * 18 * cb
+    f = W.make_format(W.WEO_F32)
+    a, b, c, d = 1 << 28, 2 << 28, 3 << 28, 4 << 28
+    assert W.weo_pack_clover(lat, f, a, W.WEO_F64, 2, b, None) == W.WEO_ERR_ARG        # invert flag
+    assert W.weo_pack_clover(lat, f, a, 7, 1, b, None) == W.WEO_ERR_ARG                # canonical precision
+    assert W.weo_pack_clover(lat, f, a, W.WEO_F64, 1, a, None) == W.WEO_ERR_ARG        # overlap
+    assert W.wilson_eo_clover_site(lat, f, 2, a, b, None, 1.0, c, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_clover_site(lat, f, 0, a, b, None, 1.0, b, 1, None) == W.WEO_ERR_ARG   # in == out
+    assert W.wilson_eo_clover_site(lat, f, 0, a + 16, b, None, 1.0, c, 1, None) == W.WEO_ERR_ALIGN
+    assert W.wilson_eo_clover_hop(lat, f, 1, 0, a, b, c, None, float("nan"), d, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_clover_apply(lat, f, 0, a, b, c, c, d, 1, None) == W.WEO_ERR_ARG       # in == out
+    assert W.wilson_eo_clover_apply(lat, f, 0, a, None, c, d, b, 1, None) == W.WEO_ERR_ARG
