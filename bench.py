@@ -13,6 +13,8 @@ The JSON line also carries:
   cpu_baseline  the FP64 NumPy oracle timed on a sample of the same workload
                 on this host (single thread);
   variants      the same apply in other storage formats;
+  clover        the even-odd operator with site-local D_ee, D_oo blocks (FP32/18
+                and FP16/12) and its mixed-precision solve;
   t_split_32x32x32x8
                 one device's share of 32^3x64 cut along t into 8 slabs: the
                 slab hop as bulk kernel + face pack + face unpack (faces
@@ -270,6 +272,37 @@ def main():
         del ud, xd, out, lo, hi
     del su, spsi
 
+    # clover-type operator (site-local D_ee, D_oo): the same lattice with
+    # random Hermitian site blocks near 1, packed as inverses
+    clover = {}
+    blocks = to_device(inputs.gen_site_blocks(DIMS, 0.3, 207))
+    for vs in ("f32/f32/18", "f16/f16/12"):
+        sp_, lp_, re_ = parse_fmt(vs)
+        f2 = Format(sp_, lp_, re_)
+        ud = lat.pack_gauge(u_dev64, f2)
+        xd = lat.pack_spinor(psi_dev64, f2)
+        clv = lat.pack_clover(blocks, f2)
+        out = lat.new_spinor(f2)
+        tmp = lat.new_spinor(f2)
+        fn = lambda: lat.clover_apply(ud, clv, xd, f2, out=out, tmp=tmp)
+        for _ in range(a.warmup):
+            fn()
+        ms = time_loop(fn, max(a.steps // 4, 1))
+        cb = 2 * 18 * 2 * REAL[lp_]                     # two blocks of 18 complex per site
+        byts = (apply_bytes_per_site(sp_, lp_, re_) + cb) * v
+        clover[vs] = {"us_per_apply": round(ms * 1e3, 2),
+                      "gflops_1320": round(FLOP_SITE * v / (ms * 1e-3) / 1e9, 1),
+                      "bytes_per_site": apply_bytes_per_site(sp_, lp_, re_) + cb,
+                      "apply_gbs": round(byts / (ms * 1e-3) / 1e9, 1),
+                      "frac_hbm": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        print(f"[bench] clover {vs}: {clover[vs]}", file=sys.stderr, flush=True)
+        del ud, xd, clv, out, tmp
+    if not a.no_solve:
+        from paper_2303_08609_amd import solve as S
+        clover["solve_1e-10"] = S.bench_clover_solve(lat, u_dev64, psi_dev64, blocks)
+        print(f"[bench] clover solves: {clover['solve_1e-10']}", file=sys.stderr, flush=True)
+    del blocks
+
     solve = None
     if not a.no_solve:
         from paper_2303_08609_amd import solve as S
@@ -311,6 +344,7 @@ def main():
                      "bytes_per_launch": hop_bytes},
         "variants": variants,
         "t_split_32x32x32x8": split,
+        "clover": clover,
     }
     if solve is not None:
         line["solve"] = solve

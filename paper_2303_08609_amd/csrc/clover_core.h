@@ -51,6 +51,33 @@ __device__ __forceinline__ void load_block(const uint8_t* base, uint32_t n, uint
     }
 }
 
+// v <- A v from the two block records already in registers.
+template <int CP, class C, class RR>
+__device__ __forceinline__ void clover_apply_raw(const RR& r0, const RR& r1, C* v) {
+    using R = decltype(C().x);
+    using CR = typename St<CP>::real;
+    C a[6], b[6], ya[6], yb[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) { a[k] = add(v[k], v[6 + k]); b[k] = sub(v[k], v[6 + k]); }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        cx<CR> w[kCloverSlots];
+        (q == 0 ? r0 : r1).unpack(w);
+        C blk[kCloverSlots];
+#pragma unroll
+        for (int k = 0; k < kCloverSlots; ++k) { blk[k].x = (R)w[k].x; blk[k].y = (R)w[k].y; }
+        herm6_mul(blk, q == 0 ? a : b, q == 0 ? ya : yb);
+    }
+    const R h = R(0.5);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        v[k].x = h * (ya[k].x + yb[k].x);
+        v[k].y = h * (ya[k].y + yb[k].y);
+        v[6 + k].x = h * (ya[k].x - yb[k].x);
+        v[6 + k].y = h * (ya[k].y - yb[k].y);
+    }
+}
+
 // v <- A v for the site matrix A of half-index i; par_base points at the
 // parity's two block fields, block_bytes is the size of one of them.
 template <int CP, class C>

@@ -9,6 +9,11 @@
 #include "clover_core.h"
 #include "hop_core.h"
 
+// WEO_CLV_PREFETCH = 0 loads the blocks after the 8 directions instead.
+#ifndef WEO_CLV_PREFETCH
+#define WEO_CLV_PREFETCH 1
+#endif
+
 namespace weo {
 
 struct CloverHopParams {
@@ -17,7 +22,29 @@ struct CloverHopParams {
     size_t block_bytes;
 };
 
-template <int SP, int LP, bool L12, bool DAG, bool AXPY, bool NORM>
+// The neighbour pipeline of the plain hop, with the two block records of the
+// site loaded in the steps whose ring slot is no longer needed (the last D
+// directions), so their latency hides behind the last directions' arithmetic.
+template <int SP, int LP, bool L12, bool DAG, bool CPH, int D, int K, class C>
+__device__ __forceinline__ void clv_step(const CloverHopParams& Q, const uint8_t* in, const Nbr& nb, uint32_t ih,
+                                         NbrRaw<SP, LP, L12> (&ring)[D + 1], RawRec<LP, kCloverSlots> (&cb)[2],
+                                         C* acc) {
+    const HopParams& P = Q.h;
+    if constexpr (K + D < 8) {
+        issue<SP, LP, L12, K + D>(P, in, nb, ih, ring[(K + D) % (D + 1)]);
+    } else if constexpr (K + D == 8) {
+        cb[0].load(Q.clv, P.g.vh, ih);
+        if constexpr (D == 1) cb[1].load(Q.clv + Q.block_bytes, P.g.vh, ih);
+    } else if constexpr (K + D == 9) {
+        cb[1].load(Q.clv + Q.block_bytes, P.g.vh, ih);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    consume<SP, LP, L12, DAG, CPH, K>(P, nb, ring[K % (D + 1)], acc);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (K + 1 < 8) clv_step<SP, LP, L12, DAG, CPH, D, K + 1>(Q, in, nb, ih, ring, cb, acc);
+}
+
+template <int SP, int LP, bool L12, bool DAG, bool AXPY, bool NORM, bool CPH>
 __global__ void __launch_bounds__(256) k_hop_clv(const CloverHopParams Q) {
     using R = typename Arith<SP>::R;
     using C = cx<R>;
@@ -35,10 +62,17 @@ __global__ void __launch_bounds__(256) k_hop_clv(const CloverHopParams Q) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = czero<C>();
         constexpr int D = hop_pipe<SP>();
+        static_assert(D == 1 || D == 2, "block prefetch placed for ring depths 1 and 2");
         NbrRaw<SP, LP, L12> ring[D + 1];
-        pipe_prologue<SP, LP, L12, DAG, true, D>(P, in, nb, ih, ring);
-        pipe_step<SP, LP, L12, DAG, true, D, 0>(P, in, nb, ih, ring, acc);
-        clover_apply_site<LP>(Q.clv, Q.block_bytes, P.g.vh, ih, acc);
+        pipe_prologue<SP, LP, L12, DAG, CPH, D>(P, in, nb, ih, ring);
+        if constexpr (WEO_CLV_PREFETCH != 0) {
+            RawRec<LP, kCloverSlots> cb[2];
+            clv_step<SP, LP, L12, DAG, CPH, D, 0>(Q, in, nb, ih, ring, cb, acc);
+            clover_apply_raw<LP>(cb[0], cb[1], acc);
+        } else {
+            pipe_step<SP, LP, L12, DAG, CPH, D, 0>(P, in, nb, ih, ring, acc);
+            clover_apply_site<LP>(Q.clv, Q.block_bytes, P.g.vh, ih, acc);
+        }
         if constexpr (AXPY) {
             C yv[12];
             load_rec<SP, 12>(P.y + (size_t)rhs * P.spinor_bytes, P.g.vh, ih, yv);
@@ -75,10 +109,13 @@ __global__ void __launch_bounds__(256) k_hop_clv(const CloverHopParams Q) {
 template <int SP, int LP, bool L12>
 static hipError_t clv_fmt(const HopLaunch& h, const CloverHopParams& Q, dim3 grid, dim3 block, hipStream_t s) {
     const bool axpy = h.y != nullptr, norm = h.partial != nullptr;
-#define WEO_CLV(D, A, N)                                                                   \
-    if (h.dagger == D && axpy == A && norm == N) {                                         \
-        hipLaunchKernelGGL((k_hop_clv<SP, LP, L12, D, A, N>), grid, block, 0, s, Q);       \
-        return hipGetLastError();                                                          \
+    bool cph = false;
+    for (int m = 0; m < 4; ++m) cph = cph || h.phase[m][1] != 0.0;
+#define WEO_CLV(D, A, N)                                                                       \
+    if (h.dagger == D && axpy == A && norm == N) {                                             \
+        if (cph) hipLaunchKernelGGL((k_hop_clv<SP, LP, L12, D, A, N, true>), grid, block, 0, s, Q);  \
+        else hipLaunchKernelGGL((k_hop_clv<SP, LP, L12, D, A, N, false>), grid, block, 0, s, Q);     \
+        return hipGetLastError();                                                              \
     }
     WEO_CLV(0, false, false) WEO_CLV(1, false, false)
     WEO_CLV(0, true, false)  WEO_CLV(1, true, false)

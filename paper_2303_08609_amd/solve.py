@@ -265,3 +265,26 @@ def bench_solves_large(dims=(48, 48, 48, 96), kappa=0.1265, eps=0.7, seed_gauge=
         if k != "dc_fp32":
             out[k]["speedup_vs_fp32_inner_cgls"] = round(base / out[k]["seconds"], 3)
     return out
+
+
+def bench_clover_solve(lat: Lattice, u_dev64, psi_dev64, blocks_dev):
+    """The clover-type system M x = b on the benchmark lattice to a true FP64
+    residual of 1e-10: FP64 defect correction around FP32 and FP16 (12-real
+    links) BiCGStab inner solves with the site blocks packed in each format."""
+    f64 = Format("f64", "f64", 18)
+    u64 = lat.pack_gauge(u_dev64, f64)
+    b64 = lat.pack_spinor(psi_dev64, f64)
+    c64 = lat.pack_clover(blocks_dev, f64)
+    out = {}
+    for name, inner, tin in (("fp32", Format("f32", "f32", 18), 1e-5), ("f16_f16link12", Format("f16", "f16", 12), 1e-3)):
+        ui = lat.pack_gauge(u_dev64, inner)
+        ci = lat.pack_clover(blocks_dev, inner)
+        run = lambda: cg(lat, f64, u64, b64, tol=1e-10, inner=inner, u_inner=ui, inner_tol=tin, maxiter=50000,
+                         max_outer=100, method="bicgstab", clover=c64, clover_inner=ci)
+        run()
+        dt, (x, info) = _timed(run)
+        out[f"dc_{name}_bicgstab"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
+                                      "outer_iters": info["outer_iters"],
+                                      "true_rel_resid_fp64": info["true_rel_resid"][0], "status": info["status"]}
+        del ui, ci
+    return out

@@ -159,3 +159,24 @@ def test_clover_argument_checks():
     with pytest.raises(WE.WilsonEOError):
         cg(lat, fmt, u, b, inner=Format("f32", "f32", 18), u_inner=lat.new_gauge(Format("f32", "f32", 18)),
            clover=clv, maxiter=1)
+
+
+@pytest.mark.parametrize("fmt_t", [FORMATS[0], FORMATS[3]], ids=["f64-18", "f32-12"])
+def test_clover_apply_complex_phases(fmt_t):
+    dims = (4, 6, 2, 8)
+    bc = tuple(np.exp(1j * np.array([0.4, -1.1, 2.0, 2.9])))
+    print(f"clover apply complex phases fmt={fmt_t}", flush=True)
+    sp, lp, reals = fmt_t
+    fmt = Format(*fmt_t)
+    lat = Lattice(dims, KAPPA, bc)
+    u = cached_gauge(dims, 0.5, 950)
+    blocks, a, ainv = _blocks(dims, 951)
+    psi = inputs.gen_spinor_half(dims, 952)
+    u_d, x_d = lat.pack_gauge(to_device(u), fmt), lat.pack_spinor(to_device(psi), fmt)
+    clv = lat.pack_clover(to_device(blocks), fmt)
+    ai_e, ai_o = full_to_half(ainv, 0), full_to_half(ainv, 1)
+    for dag in (False, True):
+        got = lat.unpack_spinor(lat.clover_apply(u_d, clv, x_d, fmt, dagger=dag), fmt).cpu().numpy()
+        want = CL.apply_m_clover(link_as_stored(u, lp, reals), ROUND[sp](psi), KAPPA, np.array(bc), ai_e, ai_o,
+                                 dagger=dag)
+        assert rel_err(got, want) <= TOL[sp], dag
