@@ -593,11 +593,18 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
         if (!p->x0_given) HIPCHK(launch_zero(x, fb, c.st));
         int inner_iters = 0, k = 0;
         bool breakdown = false;
-        std::vector<double> rel(n);
+        std::vector<double> rel(n), bb0(n);
+        HIPCHK(hipMemcpyAsync(bb0.data(), w.sc.bb, n * sizeof(double), hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
         for (;;) {
-            // r64 = b - A x; rr = ||r64||^2
-            HIPCHK(apply_op(c, p->op, id, u, x, w.t64, w.r64, w.tmp64, n, nullptr));
-            HIPCHK(launch_axpby(gb, id, n, 1.0, b, -1.0, w.t64, w.r64, w.pa, c.st));
+            // r64 = b - A x; rr = ||r64||^2.  From a zero start the residual is
+            // b itself, whose norm partials are still in pa.
+            const bool from_zero = k == 0 && !p->x0_given;
+            const void* r64 = from_zero ? b : w.r64;
+            if (!from_zero) {
+                HIPCHK(apply_op(c, p->op, id, u, x, w.t64, w.r64, w.tmp64, n, nullptr));
+                HIPCHK(launch_axpby(gb, id, n, 1.0, b, -1.0, w.t64, w.r64, w.pa, c.st));
+            }
             ScalarArgsHost sa = sargs(w.sc, n);
             sa.pa = w.pa; sa.nba = (int)nbb; sa.target = target;
             HIPCHK(launch_scalars(SCAL_SCALE, sa, c.st));
@@ -613,7 +620,7 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             }
             if (!nlive || k >= p->max_outer || inner_iters >= p->maxiter || breakdown) break;
             // inner right-hand side: r64 scaled to unit RMS, in FP32; x_acc = 0
-            HIPCHK(launch_convert(gb, id, w.r64, kAccF32, w.s_acc, n, w.sc.sc_in, 0, c.st));
+            HIPCHK(launch_convert(gb, id, r64, kAccF32, w.s_acc, n, w.sc.sc_in, 0, c.st));
             HIPCHK(launch_zero(w.x_acc, (size_t)n * spinor_field_bytes(gb, kAccF32), c.st));
             // the inner stopping test compares with ||rhs||^2 = target
             std::vector<double> tg(n, target);
@@ -629,9 +636,8 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             breakdown = breakdown || lr.breakdown;
             // x += x_acc * sc_out (only live rhs changed: x_acc = 0 elsewhere)
             HIPCHK(launch_convert(gb, kAccF32, w.x_acc, id, x, n, w.sc.sc_out, 1, c.st));
-            // restore ||b||^2
-            HIPCHK(launch_norm2(gb, id, b, n, w.pa, c.st));
-            HIPCHK(launch_reduce(w.pa, (int)nbb, n, w.sc.bb, c.st));
+            // restore ||b||^2 (bb0 outlives the copy: the next look synchronises)
+            HIPCHK(hipMemcpyAsync(w.sc.bb, bb0.data(), n * sizeof(double), hipMemcpyHostToDevice, c.st));
             ++k;
         }
         info->iters = inner_iters;
