@@ -76,6 +76,7 @@ __device__ __forceinline__ void mrhs_consume(const MrhsParams& M, const Nbr& nb,
     {
         cx<typename St<LP>::real> w[9];
         r.ln.unpack(w);
+        if constexpr (hop_pin_f16<SP, LP, L12>() && LP == P_F16) pin_values(w, L12 ? 6 : 9);
 #pragma unroll
         for (int k = 0; k < (L12 ? 6 : 9); ++k) { u[k].x = (R)w[k].x; u[k].y = (R)w[k].y; }
         if constexpr (L12) {
@@ -91,6 +92,7 @@ __device__ __forceinline__ void mrhs_consume(const MrhsParams& M, const Nbr& nb,
     for (int q = 0; q < NR; ++q) {
         C p[12];
         r.sp[q].unpack(p);
+        if constexpr (hop_pin_f16<SP, LP, L12>() && SP == P_F16) pin_values(p, 12);
         hop_dir<MU, FWD ? SF : -SF, FWD, false, C, false>(p, u, false, C{}, acc[q]);
     }
 }
@@ -219,9 +221,11 @@ __device__ __forceinline__ void lr_consume(const HopParams& P, const Nbr& nb,
     using R = decltype(C().x);
     C p[12], u[9];
     sp.unpack(p);
+    if constexpr (hop_pin_f16<SP, LP, L12>() && SP == P_F16) pin_values(p, 12);
     {
         cx<typename St<LP>::real> w[9];
         ln.unpack(w);
+        if constexpr (hop_pin_f16<SP, LP, L12>() && LP == P_F16) pin_values(w, L12 ? 6 : 9);
 #pragma unroll
         for (int k = 0; k < (L12 ? 6 : 9); ++k) { u[k].x = (R)w[k].x; u[k].y = (R)w[k].y; }
         if constexpr (L12) {
