@@ -62,10 +62,16 @@ __global__ void __launch_bounds__(256) k_hop_clv(const CloverHopParams Q) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = czero<C>();
         constexpr int D = hop_pipe<SP>();
-        static_assert(D == 1 || D == 2, "block prefetch placed for ring depths 1 and 2");
+        static_assert(D <= 2, "block prefetch placed for ring depths up to 2");
         NbrRaw<SP, LP, L12> ring[D + 1];
-        pipe_prologue<SP, LP, L12, DAG, CPH, D>(P, in, nb, ih, ring);
-        if constexpr (WEO_CLV_PREFETCH != 0) {
+        if constexpr (D > 0) pipe_prologue<SP, LP, L12, DAG, CPH, D>(P, in, nb, ih, ring);
+        if constexpr (D == 0) {
+            hop_mu<SP, LP, L12, DAG, CPH, 0>(P, in, nb, ih, acc);
+            hop_mu<SP, LP, L12, DAG, CPH, 1>(P, in, nb, ih, acc);
+            hop_mu<SP, LP, L12, DAG, CPH, 2>(P, in, nb, ih, acc);
+            hop_mu<SP, LP, L12, DAG, CPH, 3>(P, in, nb, ih, acc);
+            clover_apply_site<LP>(Q.clv, Q.block_bytes, P.g.vh, ih, acc);
+        } else if constexpr (WEO_CLV_PREFETCH != 0) {
             RawRec<LP, kCloverSlots> cb[2];
             clv_step<SP, LP, L12, DAG, CPH, D, 0>(Q, in, nb, ih, ring, cb, acc);
             clover_apply_raw<LP>(cb[0], cb[1], acc);

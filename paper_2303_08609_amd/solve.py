@@ -98,13 +98,13 @@ def bench_solves(lat: Lattice, u_np, psi_np, u_dev64, psi_dev64, reps=1):
                                    "applies": info["applies"],
                                    "true_rel_resid_fp32": info["true_rel_resid"][0],
                                    "status": info["status"]}
-    inners = {"fp32": Format("f32", "f32", 18), "bf16_f16link12": Format("bf16", "f16", 12),
-              "f16_f16link12": Format("f16", "f16", 12)}
+    inners = {"fp32": Format("f32", "f32", 18), "fp32_link12": Format("f32", "f32", 12),
+              "bf16_f16link12": Format("bf16", "f16", 12), "f16_f16link12": Format("f16", "f16", 12)}
     for name, inner in inners.items():
         ui = lat.pack_gauge(u_dev64, inner)
         for meth, tag in (("cg", ""), ("bicgstab", "_bicgstab")):
             dt, info = timed(lambda: cg(lat, f64, u64, b64, tol=1e-10, maxiter=50000, inner=inner,
-                                        u_inner=ui, inner_tol=1e-3 if name != "fp32" else 1e-5,
+                                        u_inner=ui, inner_tol=1e-3 if not name.startswith("fp32") else 1e-5,
                                         max_outer=100, method=meth))
             out[f"dc_{name}{tag}_1e-10"] = {"seconds": round(dt, 4), "inner_iters": info["iters"],
                                             "outer_iters": info["outer_iters"],
@@ -212,9 +212,10 @@ def bench_solves_12rhs(dims=(32, 32, 32, 64), kappa=0.126, eps=0.5, seed_gauge=4
     del u32
     for name, inner in (("f16_f16link12", Format("f16", "f16", 12)),
                         ("bf16_f16link12", Format("bf16", "f16", 12)),
-                        ("fp32", Format("f32", "f32", 18))):
+                        ("fp32", Format("f32", "f32", 18)),
+                        ("fp32_link12", Format("f32", "f32", 12))):
         ui = lat.pack_gauge(ud, inner)
-        tol_in = 1e-5 if name == "fp32" else 1e-3
+        tol_in = 1e-5 if name.startswith("fp32") else 1e-3
         for meth, tag in (("cg", ""), ("bicgstab", "_bicgstab")):
             cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=inner, u_inner=ui, inner_tol=tol_in,
                maxiter=50000, max_outer=100, method=meth)      # first call tunes the hop shapes
