@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the solver timings (32^3x64 single and 12 rhs, 48^3x96)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="short fixed run for rocprofv3: the 12-source 32^3x64 solve to 1e-10 "
+                         "(FP64 defect correction around FP16/12 BiCGStab), once to tune, once more")
     ap.add_argument("--profile-mode", action="store_true",
                     help="short fixed run for rocprofv3: a 1 GiB device copy (counter "
                          "calibration) and --steps hop launches per format, nothing else")
@@ -141,6 +144,20 @@ def main():
     from paper_2303_08609_amd.ops import Format, Lattice, to_device
 
     torch.cuda.set_device(0)
+    if a.profile_solve:
+        from paper_2303_08609_amd.solve import cg
+        lat12 = Lattice(DIMS, KAPPA, (1, 1, 1, -1))
+        ud = to_device(inputs.gen_gauge(DIMS, EPS, 401))
+        f64, fi = Format("f64", "f64", 18), Format("f16", "f16", 12)
+        u64, ui = lat12.pack_gauge(ud, f64), lat12.pack_gauge(ud, fi)
+        b12 = lat12.pack_spinor(to_device(inputs.gen_point_noise_sources(DIMS, 406)), f64)
+        for k in range(2):
+            x, info = cg(lat12, f64, u64, b12, nrhs=12, tol=1e-10, inner=fi, u_inner=ui, inner_tol=1e-3,
+                         maxiter=50000, max_outer=100, method="bicgstab")
+            torch.cuda.synchronize()
+            print(f"[bench] profiled 12-rhs solve {k}: {info['seconds']:.4f} s, inner {info['iters']}, "
+                  f"outer {info['outer_iters']}", file=sys.stderr, flush=True)
+        return
     lat = Lattice(DIMS, KAPPA, (1, 1, 1, -1))
     v = lat.volume
     t0 = time.perf_counter()
@@ -260,9 +277,21 @@ def main():
             pack()
             bulk()
             unpack()
+        side = torch.cuda.Stream()          # default priority
+
+        def overlapped():
+            # faces packed on a second stream while the bulk kernel runs, as
+            # a sharded hop would post them before its interior work
+            side.wait_stream(stream)
+            with torch.cuda.stream(side):
+                pack()
+            bulk()
+            stream.wait_stream(side)
+            unpack()
         r = {}
         for name, fn in (("periodic_hop_us", plain), ("bulk_hop_us", bulk), ("face_pack_us", pack),
-                         ("face_unpack_us", unpack), ("pack_bulk_unpack_us", whole)):
+                         ("face_unpack_us", unpack), ("pack_bulk_unpack_us", whole),
+                         ("pack_overlapped_bulk_unpack_us", overlapped)):
             for _ in range(a.warmup):
                 fn()
             r[name] = round(time_loop(fn, n) * 1e3, 2)
