@@ -123,8 +123,11 @@ int weo_format_supported(const weo_format* fmt);
 int weo_set_mrhs_shape(int nr, int sites, int persist, int bz, int split);
 
 /* The autotuner's cached choices as JSON lines in buf (NUL-terminated,
- * truncated to len bytes); returns the untruncated length.  buf may be NULL
- * to query the length. */
+ * truncated to len bytes), one per (lattice, format, nrhs, epilogue: 1 axpy,
+ * 2 norm partials); returns the untruncated length.  buf may be NULL to
+ * query the length.  A multi-rhs launch is tuned on its first call by
+ * timing every candidate shape on the caller's stream and buffers, except
+ * an in-place axpy (y is out), which runs untuned. */
 int weo_tuning_report(char* buf, size_t len);
 
 /* Bytes of the packed gauge field (all 4V links) in format fmt; 0 on error. */

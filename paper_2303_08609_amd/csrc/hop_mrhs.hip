@@ -457,7 +457,8 @@ hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) 
 
 namespace {
 
-using TuneKey = std::tuple<int, int, int, int, int, int>;   // dims, format, nrhs
+// dims, format, nrhs, epilogue (1: axpy, 2: norm partials)
+using TuneKey = std::tuple<int, int, int, int, int, int, int>;
 
 struct TuneEntry {
     MrhsCfg cfg;       // nr == 1: the single-rhs kernel
@@ -583,13 +584,21 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
         if (c.nr > h.nrhs) c.nr = h.nrhs;
         return c.nr <= 1 ? launch_hop_single(h, s) : launch_hop_mrhs(h, c, s);
     }
-    const TuneKey key{h.g.lx, h.g.ly, h.g.lz, h.g.lt, h.fmt, h.nrhs};
+    const int epi = (h.y != nullptr ? 1 : 0) + (h.partial != nullptr ? 2 : 0);
+    const TuneKey key{h.g.lx, h.g.ly, h.g.lz, h.g.lt, h.fmt, h.nrhs, epi};
     TuneEntry e;
     bool have = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
         if (it != g_tune.end()) { e = it->second; have = true; }
+    }
+    if (!have && h.y != nullptr) {
+        // an in-place axpy (y is out) cannot be timed by repeated launches:
+        // each would add to the previous result.  Run it untuned.
+        const size_t fb = (size_t)h.nrhs * spinor_field_bytes(h.g, h.fmt);
+        const uintptr_t y = reinterpret_cast<uintptr_t>(h.y), o = reinterpret_cast<uintptr_t>(h.out);
+        if (y < o + fb && o < y + fb) return launch_hop_single(h, s);
     }
     if (!have) {
         if (tuning_enabled()) {
@@ -613,10 +622,11 @@ int tuning_report(char* buf, size_t len) {
         const TuneKey& k = kv.first;
         const TuneEntry& e = kv.second;
         const int n = snprintf(buf ? buf + off : nullptr, buf && off < len ? len - off : 0,
-                               "{\"dims\":[%d,%d,%d,%d],\"fmt\":%d,\"nrhs\":%d,\"nr\":%d,\"sites\":%d,"
-                               "\"persist\":%d,\"bz\":%d,\"split\":%d,\"us\":%.2f}\n",
+                               "{\"dims\":[%d,%d,%d,%d],\"fmt\":%d,\"nrhs\":%d,\"epilogue\":%d,\"nr\":%d,"
+                               "\"sites\":%d,\"persist\":%d,\"bz\":%d,\"split\":%d,\"us\":%.2f}\n",
                                std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
-                               std::get<5>(k), e.cfg.nr, e.cfg.s, e.cfg.persist, e.cfg.bz, e.cfg.split, e.us);
+                               std::get<5>(k), std::get<6>(k), e.cfg.nr, e.cfg.s, e.cfg.persist, e.cfg.bz,
+                               e.cfg.split, e.us);
         if (n > 0) off += (size_t)n;
     }
     return (int)off;

@@ -75,3 +75,25 @@ def test_bad_shape_rejected():
     assert WE.weo_set_mrhs_shape(2, 64, 2, 0, 0) == WE.WEO_ERR_ARG
     assert WE.weo_set_mrhs_shape(2, 64, 0, -1, 0) == WE.WEO_ERR_ARG
     assert WE.weo_set_mrhs_shape(2, 64, 0, 0, 2) == WE.WEO_ERR_ARG
+
+
+def test_in_place_axpy_on_an_untuned_shape():
+    """out = out + alpha hop(in) with 12 right-hand sides on a lattice no
+    launch has tuned yet: the tuner must not time it by repeated launches
+    (each would add to the last), so the result is one application."""
+    dims = (6, 4, 4, 8)
+    print("in-place axpy, untuned 12 rhs", flush=True)
+    lat, fmt, u_d, x_d, u_o, psi_o = _setup(dims, ("f64", "f64", 18), 12, seed=730)
+    WE.weo_set_mrhs_shape(0, 0, 0, 0, 0)
+    y = inputs.gen_spinor_half(dims, 731, nrhs=12)
+    y_d = lat.pack_spinor(to_device(y), fmt)
+    lat.hop_axpy(u_d, x_d, y_d, fmt, out_parity=1, alpha=0.3, nrhs=12, out=y_d)
+    got = lat.unpack_spinor(y_d, fmt, nrhs=12).cpu().numpy()
+    ph = np.array(AP, dtype=np.complex128)
+    for r in range(12):
+        want = y[r] + 0.3 * W.hop_eo(u_o, psi_o[r], 0, ph)
+        assert rel_err(got[r], want) <= 1e-12, r
+    # the out-of-place launch of the same shape tunes and agrees
+    out = lat.hop_axpy(u_d, x_d, lat.pack_spinor(to_device(y), fmt), fmt, out_parity=1, alpha=0.3, nrhs=12)
+    assert rel_err(lat.unpack_spinor(out, fmt, nrhs=12).cpu().numpy(), got) <= 1e-13
+    assert '"epilogue":1' in WE.tuning_report()
