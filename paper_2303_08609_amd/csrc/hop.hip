@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_ho
                 acc[k].y = fma(a, acc[k].y, yv[k].y);
             }
         }
-        store_rec<SP, 12>(out, P.g.vh, ih, acc);
+        store_rec<SP, 12, C, hop_nt_store<SP>()>(out, P.g.vh, ih, acc);
         if constexpr (NORM) {
             // norm of the value as stored (rounded to the storage precision)
             C st[12];

@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(256) k_hop_clv(const CloverHopParams Q) {
                 acc[k].y = fma(a, acc[k].y, yv[k].y);
             }
         }
-        store_rec<SP, 12>(out, P.g.vh, ih, acc);
+        store_rec<SP, 12, C, hop_nt_store<SP>()>(out, P.g.vh, ih, acc);
         if constexpr (NORM) {
             C st[12];
             if constexpr (SP == P_F64 || SP == P_F32) {

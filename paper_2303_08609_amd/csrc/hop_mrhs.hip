@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
                         }
                     }
                     uint8_t* out = P.out + (size_t)r * P.spinor_bytes;
-                    store_rec<SP, 12>(out, P.g.vh, ih, acc[q]);
+                    store_rec<SP, 12, C, hop_nt_store<SP>()>(out, P.g.vh, ih, acc[q]);
                     if (P.partial) {
                         C st[12];
                         if constexpr (SP == P_F64 || SP == P_F32) {

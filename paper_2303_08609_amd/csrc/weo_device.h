@@ -259,13 +259,21 @@ __device__ __forceinline__ void round_rec(const V* in, V* out) {
     if constexpr (T::TAILB == 4) St<P>::unpack4(St<P>::pack4(in + T::NFULL * T::K), out + T::NFULL * T::K);
 }
 
-template <int P, int NC, class V>
+template <int P, int NC, class V, bool NT = false>
 __device__ __forceinline__ void store_rec(uint8_t* __restrict__ base, uint32_t n, uint32_t i, const V* v) {
     using T = Rec<P, NC>;
     const size_t pb = (size_t)n * 16;
 #pragma unroll
-    for (int p = 0; p < T::NFULL; ++p)
-        *reinterpret_cast<uint4*>(base + p * pb + (uint32_t)(i * 16u)) = St<P>::pack16(v + p * T::K);
+    for (int p = 0; p < T::NFULL; ++p) {
+        const uint4 w = St<P>::pack16(v + p * T::K);
+        if constexpr (NT) {
+            u32x4_t x;
+            x.x = w.x; x.y = w.y; x.z = w.z; x.w = w.w;
+            __builtin_nontemporal_store(x, reinterpret_cast<u32x4_t*>(base + p * pb + (uint32_t)(i * 16u)));
+        } else {
+            *reinterpret_cast<uint4*>(base + p * pb + (uint32_t)(i * 16u)) = w;
+        }
+    }
     if constexpr (T::TAILB == 8) {
         *reinterpret_cast<uint2*>(base + T::NFULL * pb + (uint32_t)(i * 8u)) = St<P>::pack8(v + T::NFULL * T::K);
     } else if constexpr (T::TAILB == 4) {
