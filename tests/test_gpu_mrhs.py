@@ -97,3 +97,36 @@ def test_in_place_axpy_on_an_untuned_shape():
     out = lat.hop_axpy(u_d, x_d, lat.pack_spinor(to_device(y), fmt), fmt, out_parity=1, alpha=0.3, nrhs=12)
     assert rel_err(lat.unpack_spinor(out, fmt, nrhs=12).cpu().numpy(), got) <= 1e-13
     assert '"epilogue":1' in WE.tuning_report()
+
+
+
+@pytest.mark.parametrize("fmt_t", [("f32", "f32", 18), ("f16", "f16", 12)], ids=["f32-18", "f16-12"])
+def test_twelve_rhs_32_3x64_sampled(fmt_t):
+    """The 12-source workload at full size (32^3x64, point + noise sources,
+    links exp(0.5 i H)) through the tuned multi-RHS hop and apply, as the
+    benchmark and the batched solves launch them; every source checked at
+    sampled sites (faces, corners, the point's neighbours, random) against the
+    oracle."""
+    from tests._helpers import cached_gauge
+    from tests.test_gpu_apply import _sample_sites
+    dims = (32, 32, 32, 64)
+    print(f"12 rhs 32^3x64 sampled fmt={fmt_t}", flush=True)
+    sp, lp, reals = fmt_t
+    fmt = Format(*fmt_t)
+    lat = Lattice(dims, 0.126, AP)
+    u = cached_gauge(dims, 0.5, 401)
+    b = inputs.gen_point_noise_sources(dims, 406)
+    WE.weo_set_mrhs_shape(0, 0, 0, 0, 0)
+    ud, bd = lat.pack_gauge(to_device(u), fmt), lat.pack_spinor(to_device(b), fmt)
+    hop = lat.unpack_spinor(lat.hop(ud, bd, fmt, out_parity=1, nrhs=12), fmt, nrhs=12).cpu().numpy()
+    app = lat.unpack_spinor(lat.apply(ud, bd, fmt, nrhs=12), fmt, nrhs=12).cpu().numpy()
+    hop, app = hop.reshape(12, -1, 4, 3), app.reshape(12, -1, 4, 3)
+    del ud, bd
+    sites = _sample_sites(dims, 12, 9)
+    u_or, b_or = link_as_stored(u, lp, reals), ROUND[sp](b)
+    ph = np.array(AP, dtype=np.complex128)
+    for r in range(12):
+        want = W.hop_at_sites(u_or, b_or[r], 0, ph, sites)
+        assert rel_err(hop[r][sites], want) <= TOL[sp], ("hop", r)
+        want = W.apply_m_at_sites(u_or, b_or[r], 0.126, ph, sites)
+        assert rel_err(app[r][sites], want) <= TOL[sp], ("apply", r)
