@@ -9,6 +9,10 @@ algorithm.  The oracle uses the standard ones:
 * CG on the Hermitian positive definite operator A = M^dag M to solve A x = b;
 * BiCGStab (van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992) 631) on M
   itself, for non-Hermitian M;
+* block CG for several right-hand sides at once (O'Leary, Linear Algebra
+  Appl. 29 (1980) 293) in the QR-retooled form of Dubrulle (Electron. Trans.
+  Numer. Anal. 12 (2001) 216), on A = M^dag M directly or, for M x = b, on the
+  normal equations while carrying S = B - M X;
 * defect correction (iterative refinement): x += solve(b - M x) with the inner
   solve run to a loose relative tolerance;
 * dense ``numpy.linalg.solve`` on tiny lattices.
@@ -120,6 +124,72 @@ def bicgstab(apply_a, b, tol, maxiter, x0=None):
         it += 1
         hist.append(np.sqrt(norm2(r)) / bnorm)
     return x, it, hist
+
+
+def _block_qr(z):
+    """Thin Householder QR of the n x s block z (columns are the rhs)."""
+    q, r = np.linalg.qr(z, mode="reduced")
+    return q, r
+
+
+def block_cg(apply_a, b, tol, maxiter, apply_m=None, apply_mdag=None):
+    """Block CG for s right-hand sides, Dubrulle's QR form.
+
+    ``b`` is a list of s one-parity arrays.  Without ``apply_m`` it solves
+    A X = B for Hermitian positive definite ``apply_a``.  With ``apply_m`` and
+    ``apply_mdag`` it solves M X = B through A = M^dag M, M^dag B and also
+    carries S = B - M X.
+
+    The residual block of the system solved is kept as R = Q C with Q
+    orthonormal (n x s) and C (s x s); the search block P satisfies P^H Q = I:
+        start   Q C = R_0 (QR),  P = Q
+        repeat  W = A P,  delta = (P^H W)^-1
+                X += P delta C       (S -= (M P) delta C)
+                Q' psi = Q - W delta (QR),  C = psi C
+                P = Q' + P psi^H,    Q = Q'
+    X_k is the Galerkin solution over the block Krylov space of R_0.  Stops
+    when every column meets ||r_j|| <= tol ||b_j|| (r = S for M x = b, else
+    the recurrence ||r_j|| = ||C[:, j]||).  Returns (X as a list, iterations,
+    history of the largest relative residual).
+    """
+    shape = b[0].shape
+    s = len(b)
+    bm = np.stack([v.reshape(-1) for v in b], axis=1)
+    bnorm = np.linalg.norm(bm, axis=0)
+    normal = apply_m is not None
+
+    def blk(f, m):
+        return np.stack([f(m[:, j].reshape(shape)).reshape(-1) for j in range(m.shape[1])], axis=1)
+
+    x = np.zeros_like(bm)
+    sres = bm.copy()
+    r0 = blk(apply_mdag, bm) if normal else bm.copy()
+    q, c = _block_qr(r0)
+    p = q.copy()
+
+    def rel():
+        res = np.linalg.norm(sres, axis=0) if normal else np.linalg.norm(c, axis=0)
+        return float(np.max(res / bnorm))
+
+    hist = [rel()]
+    it = 0
+    while hist[-1] > tol and it < maxiter:
+        if normal:
+            mp = blk(apply_m, p)
+            w = blk(apply_mdag, mp)
+        else:
+            w = blk(apply_a, p)
+        delta = np.linalg.inv(p.conj().T @ w)
+        x = x + p @ (delta @ c)
+        if normal:
+            sres = sres - mp @ (delta @ c)
+        q_new, psi = _block_qr(q - w @ delta)
+        c = psi @ c
+        p = q_new + p @ psi.conj().T
+        q = q_new
+        it += 1
+        hist.append(rel())
+    return [x[:, j].reshape(shape) for j in range(s)], it, hist
 
 
 def defect_correction(apply_m, inner_solve, b, tol, max_outer, x0=None):

@@ -115,3 +115,76 @@ def test_bicgstab_iterates_equal_scipy():
         x, it, _ = S.bicgstab(lambda v: a @ v, b, 1e-30, k)
         xs, _ = spl.bicgstab(a, b, x0=np.zeros(n, complex), rtol=1e-30, atol=0.0, maxiter=k)
         assert it == k and np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-13, k
+
+
+def _hpd(n, seed, shift=0.5):
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    return g @ g.conj().T / n + shift * np.eye(n)
+
+
+def test_block_cg_iterates_are_the_block_krylov_galerkin_solutions():
+    """After k steps every column of X_k minimises the A-norm error over the
+    whole block Krylov space span{R_0, A R_0, ..., A^(k-1) R_0}: a projection
+    computed densely, independently of the recurrences."""
+    n, s = 40, 3
+    a = _hpd(n, 5)
+    rng = np.random.default_rng(6)
+    b = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for _ in range(s)]
+    bm = np.stack(b, axis=1)
+    for k in (1, 2, 3, 4):
+        x, it, _ = S.block_cg(lambda v: a @ v, b, 1e-30, k)
+        assert it == k
+        kry = np.concatenate([np.linalg.matrix_power(a, i) @ bm for i in range(k)], axis=1)
+        v, _ = np.linalg.qr(kry)
+        want = v @ np.linalg.solve(v.conj().T @ a @ v, v.conj().T @ bm)
+        got = np.stack(x, axis=1)
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-11, k
+
+
+def test_block_cg_finite_termination():
+    """With s right-hand sides the block Krylov space fills R^n after n / s
+    steps, so block CG is exact after 6 steps on a 24 x 24 system with 4."""
+    n, s = 24, 4
+    a = _hpd(n, 7, shift=1.0)
+    rng = np.random.default_rng(8)
+    b = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for _ in range(s)]
+    x, it, hist = S.block_cg(lambda v: a @ v, b, 1e-11, 50)
+    assert it <= n // s
+    for xj, bj in zip(x, b):
+        assert np.linalg.norm(a @ xj - bj) / np.linalg.norm(bj) < 1e-10
+
+
+def test_block_cg_one_rhs_iterates_equal_scipy_cg():
+    """With one right-hand side block CG is CG: the iterates equal SciPy's."""
+    import scipy.sparse.linalg as spl
+    n = 30
+    a = _hpd(n, 9)
+    rng = np.random.default_rng(10)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    for k in (1, 2, 4, 7):
+        x, it, _ = S.block_cg(lambda v: a @ v, [b], 1e-30, k)
+        xs, _ = spl.cg(a, b, x0=np.zeros(n, complex), rtol=1e-30, atol=0.0, maxiter=k)
+        assert it == k and np.linalg.norm(x[0] - xs) / np.linalg.norm(xs) < 1e-12, k
+
+
+def test_block_cg_normal_equations_on_the_wilson_operator():
+    """M X = B through M^dag M: the iterates equal block CG run on
+    (M^dag M, M^dag B), the carried S is the true residual B - M X, and the
+    converged X is the dense solution."""
+    u, _, m, md, dims, kappa = _setup()
+    b = [inputs.gen_spinor_half(dims, 140 + j) for j in range(3)]
+    mdm = lambda v: md(m(v))
+    for k in (1, 3):
+        x, it, hist = S.block_cg(None, b, 1e-30, k, apply_m=m, apply_mdag=md)
+        xa, _, _ = S.block_cg(mdm, [md(v) for v in b], 1e-30, k)
+        for j in range(3):
+            assert np.linalg.norm(x[j] - xa[j]) / np.linalg.norm(xa[j]) < 1e-10, (k, j)
+        true = max(S.rel_resid(m, x[j], b[j]) for j in range(3))
+        assert abs(hist[-1] - true) <= 1e-10 * true, k
+    x, it, hist = S.block_cg(None, b, 1e-11, 500, apply_m=m, apply_mdag=md)
+    d = _dense_m(u, kappa, PH, dims)
+    for j in range(3):
+        assert S.rel_resid(m, x[j], b[j]) <= 1e-11
+        want = np.linalg.solve(d, b[j].reshape(-1)).reshape(b[j].shape)
+        assert np.linalg.norm(x[j] - want) / np.linalg.norm(want) < 1e-9
