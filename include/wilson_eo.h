@@ -283,6 +283,14 @@ int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger,
 #define WEO_SOLVER_BICGSTAB  1   /* BiCGStab (van der Vorst 1992) on the operator itself:
                                     two operator products per iteration, complex
                                     scalars, FP64 dot products */
+#define WEO_SOLVER_BLOCK_CG  2   /* block CG (O'Leary 1980) in Dubrulle's QR form
+                                    (2001): the live rhs share one block Krylov
+                                    space; CG on M^dag M for WEO_OP_MDAGM, on the
+                                    normal equations (carrying b - M x) for
+                                    WEO_OP_M / WEO_OP_DW.  FP64 or FP32 vectors
+                                    only (a mixed solve needs FP32 inner spinors);
+                                    WEO_BREAKDOWN when the block loses rank (e.g.
+                                    two equal rhs) */
 
 typedef struct {
     int        op;          /* WEO_OP_M, WEO_OP_MDAGM or WEO_OP_DW */
@@ -297,8 +305,9 @@ typedef struct {
     double     inner_tol;   /* relative tolerance of each inner solve */
     int        max_outer;   /* cap on defect-correction steps */
     int        check_every; /* iterations between host convergence checks (>=1) */
-    int        method;      /* WEO_SOLVER_CG or WEO_SOLVER_BICGSTAB (also for the
-                               inner solves of defect correction) */
+    int        method;      /* WEO_SOLVER_CG, WEO_SOLVER_BICGSTAB or
+                               WEO_SOLVER_BLOCK_CG (also for the inner solves of
+                               defect correction) */
     const void* clover;     /* NULL: Wilson (D_ee = D_oo = 1).  Else packed INVERSE
                                site blocks (weo_pack_clover, invert = 1) in format
                                fmt: the operator is the clover-type M of

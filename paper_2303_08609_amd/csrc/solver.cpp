@@ -21,6 +21,14 @@
 //     v = A p;  alpha = rho / <r^, v>;  s = r - alpha v;  t = A s;
 //     omega = <t, s> / ||t||^2;  x += alpha p + omega s;  r = s - omega t;
 //     rho' = <r^, r>;  beta = (rho' / rho)(alpha / omega);  p = r + beta (p - omega v)
+//  Block CG (method WEO_SOLVER_BLOCK_CG; O'Leary 1980, in the QR form of
+//  Dubrulle 2001) for the s live right-hand sides together, on A = M^dag M
+//  (for M x = b and D_W through the normal equations, carrying S = B - M X):
+//     Q C = R_0 (QR),  P = Q
+//     repeat: W = A P;  delta = (P^H W)^-1;  X += P delta C;  S -= (M P) delta C
+//             Q' psi = Q - W delta (QR);  C = psi C;  P = Q' + P psi^H;  Q = Q'
+//  The QR factorisations are Cholesky QR (Gram matrix on the device in FP64,
+//  Cholesky factor on the host); the s x s algebra runs on the host in FP64.
 //  With site blocks (clover-type D_ee, D_oo; packed inverse blocks C) the
 //  operator is M = 1 - kappa^2 C_e H_eo C_o H_oe of Eq. (4), same solvers.
 //  Defect correction (mixed precision): in FP64, r = b - A x; the residual is
@@ -36,6 +44,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -82,12 +91,14 @@ struct Workspace {
     void *rh, *s2;                                        // BiCGStab: shadow residual (op), s (acc)
     void *r64, *t64, *tmp64;                              // outer (mixed) vectors
     double *pa, *pb, *pc;                                 // partial sums
+    double *gpart, *upart, *gram, *tm;                    // block CG: partials, Gram, s x s factors
     Scalars sc;
     size_t bytes;
 };
 
 // The format used for FP32 accumulation vectors (spinor part only matters).
 constexpr int kAccF32 = FMT_S_S_18;
+constexpr int kBlockFactors = 5;      // s x s factors of block CG held on the device
 
 uint32_t max_partials(const Geom& g) {
     const uint32_t a = (g.vh + 63) / 64;           // smallest legal hop workgroup
@@ -116,6 +127,12 @@ Workspace carve_ws(const Geom& g, int fmt, const weo_solver_params* p, int inner
     if (p->method == WEO_SOLVER_BICGSTAB) {
         w.rh = c.take(fo);
         w.s2 = c.take(fa);
+    }
+    if (p->method == WEO_SOLVER_BLOCK_CG) {
+        w.gpart = static_cast<double*>(c.take((size_t)block_gram_wg(g, op) * kGramStride * sizeof(double)));
+        w.upart = static_cast<double*>(c.take((size_t)kMaxBlock * block_update_wg(g, op) * sizeof(double)));
+        w.gram = static_cast<double*>(c.take(kGramStride * sizeof(double)));
+        w.tm = static_cast<double*>(c.take(kBlockFactors * kGramStride * sizeof(double)));
     }
     if (p->mixed) {
         const size_t f64 = (size_t)n * spinor_field_bytes(g, fmt);
@@ -439,11 +456,219 @@ int run_level_bicg(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, 
     return WEO_OK;
 }
 
+// ---- block CG ---------------------------------------------------------------
+// Small dense complex algebra for the s x s factors, FP64 on the host; row-major.
+using cplx = std::complex<double>;
+struct Mat {
+    int n;
+    std::vector<cplx> a;
+    explicit Mat(int n_) : n(n_), a((size_t)n_ * n_) {}
+    cplx& operator()(int i, int j) { return a[(size_t)i * n + j]; }
+    cplx operator()(int i, int j) const { return a[(size_t)i * n + j]; }
+    static Mat eye(int n) {
+        Mat m(n);
+        for (int i = 0; i < n; ++i) m(i, i) = 1.0;
+        return m;
+    }
+};
+Mat mul(const Mat& x, const Mat& y) {
+    Mat z(x.n);
+    for (int i = 0; i < x.n; ++i)
+        for (int k = 0; k < x.n; ++k)
+            for (int j = 0; j < x.n; ++j) z(i, j) += x(i, k) * y(k, j);
+    return z;
+}
+Mat adj(const Mat& x) {
+    Mat z(x.n);
+    for (int i = 0; i < x.n; ++i)
+        for (int j = 0; j < x.n; ++j) z(i, j) = std::conj(x(j, i));
+    return z;
+}
+// From the device layout (re, im interleaved, G[j][k] = <a_j, b_k>), made
+// exactly Hermitian.
+Mat gram_from(const std::vector<double>& g, int n) {
+    Mat m(n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) m(i, j) = cplx(g[(i * n + j) * 2], g[(i * n + j) * 2 + 1]);
+    Mat h(n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) h(i, j) = 0.5 * (m(i, j) + std::conj(m(j, i)));
+    return h;
+}
+// G = L L^H.  False unless every pivot exceeds rank_eps times its diagonal
+// entry (the squared sine of the angle between a column and the span of the
+// ones before it): a rank-deficient block, to the vectors' precision.
+bool cholesky(const Mat& gm, Mat& l, double rank_eps) {
+    const int n = gm.n;
+    l = Mat(n);
+    for (int j = 0; j < n; ++j) {
+        double d = gm(j, j).real();
+        for (int k = 0; k < j; ++k) d -= std::norm(l(j, k));
+        if (!(d > rank_eps * gm(j, j).real()) || !std::isfinite(d)) return false;
+        l(j, j) = std::sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            cplx v = gm(i, j);
+            for (int k = 0; k < j; ++k) v -= l(i, k) * std::conj(l(j, k));
+            l(i, j) = v / l(j, j).real();
+        }
+    }
+    return true;
+}
+// inverse of a lower triangular matrix
+Mat lower_inv(const Mat& l) {
+    const int n = l.n;
+    Mat x(n);
+    for (int j = 0; j < n; ++j) {
+        x(j, j) = 1.0 / l(j, j);
+        for (int i = j + 1; i < n; ++i) {
+            cplx v = 0.0;
+            for (int k = j; k < i; ++k) v -= l(i, k) * x(k, j);
+            x(i, j) = v / l(i, i);
+        }
+    }
+    return x;
+}
+void to_dev_layout(const Mat& m, double* out) {
+    for (int i = 0; i < m.n; ++i)
+        for (int j = 0; j < m.n; ++j) {
+            out[(i * m.n + j) * 2] = m(i, j).real();
+            out[(i * m.n + j) * 2 + 1] = m(i, j).imag();
+        }
+}
+
+// Block CG at one precision level (vectors in one FP64 or FP32 format).  Same
+// contract as run_level: x_acc holds the start, s_acc the residual b - M x
+// (b - A x for M^dag M), mask the live rhs, bb[r] = ||b||^2.  The live rhs
+// form one block; it stops when every one of them meets ||r||^2 <= tol^2 bb
+// (r = S, or the recurrence ||C e_j||^2 for M^dag M).  Block vectors: Q = r,
+// P = p, W = q, M P = t (fields 0 .. s-1).  Breakdown: a Gram matrix that is
+// not numerically positive definite (rank loss of the block).
+int run_level_block(Ctx& c, const Workspace& w, int op, int fmt, const void* u, void* x_acc, int nrhs,
+                    double tol, int maxiter, LevelResult* res) {
+    const Geom& g = c.gb;
+    const size_t fb = spinor_field_bytes(g, fmt);
+    res->iters = 0;
+    res->breakdown = 0;
+    std::vector<int> mask(nrhs);
+    std::vector<double> bb(nrhs);
+    HIPCHK(hipMemcpyAsync(mask.data(), w.sc.mask, nrhs * sizeof(int), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(bb.data(), w.sc.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    // rhs whose start already meets the tolerance stay out of the block
+    std::vector<double> ss0(nrhs);
+    HIPCHK(launch_norm2(g, fmt, w.s_acc, nrhs, w.pb, c.st));
+    HIPCHK(launch_reduce(w.pb, (int)blas_blocks(g), nrhs, w.sc.rr, c.st));
+    HIPCHK(hipMemcpyAsync(ss0.data(), w.sc.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    std::vector<int> live;
+    for (int r = 0; r < nrhs; ++r)
+        if (mask[r] && !(ss0[r] <= tol * tol * bb[r])) live.push_back(r);
+    const int s = (int)live.size();
+    if (!s) return WEO_OK;
+    const bool normal = op != WEO_OP_MDAGM;
+    // 64 unit roundoffs of the vector format
+    const double rank_eps = 64.0 * (fmt_info(fmt).spinor_prec == WEO_F64 ? 0x1p-53 : 0x1p-24);
+    auto ref = [&](void* base, bool mapped) {
+        BlockRef b;
+        std::memset(&b, 0, sizeof(b));
+        b.base = static_cast<uint8_t*>(base);
+        b.stride = fb;
+        for (int j = 0; j < s; ++j) b.col[j] = (uint8_t)(mapped ? live[j] : j);
+        return b;
+    };
+    const BlockRef X = ref(x_acc, true), S = ref(w.s_acc, true);
+    const BlockRef Q = ref(w.r, false), P = ref(w.p, false), W = ref(w.q, false), MP = ref(w.t, false);
+    const double tol2 = tol * tol;
+    // host copies of the factors: each is rewritten only after a stream
+    // synchronisation that follows its last upload
+    std::vector<double> h_id(kGramStride), h_dc(kGramStride), h_dl(kGramStride), h_pi(kGramStride),
+        h_ph(kGramStride), gh(kGramStride), ssv(s);
+    double* d_id = w.tm;
+    double* d_dc = w.tm + kGramStride;
+    double* d_dl = w.tm + 2 * kGramStride;
+    double* d_pi = w.tm + 3 * kGramStride;
+    double* d_ph = w.tm + 4 * kGramStride;
+    auto upload = [&](const Mat& m, std::vector<double>& h, double* d) -> hipError_t {
+        to_dev_layout(m, h.data());
+        return hipMemcpyAsync(d, h.data(), (size_t)2 * s * s * sizeof(double), hipMemcpyHostToDevice, c.st);
+    };
+    auto gram = [&](const BlockRef& a, const BlockRef& b, Mat& out) -> hipError_t {
+        hipError_t e = launch_block_gram(g, fmt, s, a, b, w.gpart, w.gram, c.st);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(gh.data(), w.gram, (size_t)2 * s * s * sizeof(double), hipMemcpyDeviceToHost, c.st);
+        if (e != hipSuccess) return e;
+        if (normal) {
+            e = hipMemcpyAsync(ssv.data(), w.sc.ss, s * sizeof(double), hipMemcpyDeviceToHost, c.st);
+            if (e != hipSuccess) return e;
+        }
+        e = hipStreamSynchronize(c.st);
+        out = gram_from(gh, s);
+        return e;
+    };
+    HIPCHK(upload(Mat::eye(s), h_id, d_id));
+    // R_0 = S (M^dag M) or A^dag S, gathered into Q; ||S_j||^2 into ss
+    if (normal) {
+        HIPCHK(launch_block_update(g, fmt, s, MP, nullptr, S, 1.0, d_id, w.upart, w.sc.ss, c.st));
+        HIPCHK(apply_a(c, fmt, u, 1, w.t, w.r, w.tmp, s, nullptr));
+    } else {
+        HIPCHK(launch_block_update(g, fmt, s, Q, nullptr, S, 1.0, d_id, nullptr, nullptr, c.st));
+    }
+    Mat gm(s), l(s);
+    HIPCHK(gram(Q, Q, gm));
+    if (!cholesky(gm, l, rank_eps)) { res->breakdown = 1; return WEO_OK; }
+    Mat cm = adj(l);                                   // C = psi_0 (R_0 = Q C)
+    HIPCHK(upload(adj(lower_inv(l)), h_pi, d_pi));     // Q = R_0 psi_0^-1
+    HIPCHK(launch_block_update(g, fmt, s, Q, nullptr, Q, 1.0, d_pi, nullptr, nullptr, c.st));
+    HIPCHK(launch_block_update(g, fmt, s, P, nullptr, Q, 1.0, d_id, nullptr, nullptr, c.st));
+    auto converged = [&]() {
+        for (int j = 0; j < s; ++j) {
+            double rr = 0.0;
+            if (normal) rr = ssv[j];
+            else
+                for (int i = 0; i < s; ++i) rr += std::norm(cm(i, j));
+            if (!(rr <= tol2 * bb[live[j]])) return false;
+        }
+        return true;
+    };
+    if (converged()) return WEO_OK;
+    for (int it = 1; it <= maxiter; ++it) {
+        // W = A P (M P kept for S)
+        if (normal) {
+            HIPCHK(apply_a(c, fmt, u, 0, w.p, w.t, w.tmp, s, nullptr));
+            HIPCHK(apply_a(c, fmt, u, 1, w.t, w.q, w.tmp, s, nullptr));
+        } else {
+            HIPCHK(apply_op(c, op, fmt, u, w.p, w.q, w.t, w.tmp, s, nullptr));
+        }
+        HIPCHK(gram(P, W, gm));
+        if (!cholesky(gm, l, rank_eps)) { res->breakdown = 1; break; }
+        const Mat li = lower_inv(l);
+        const Mat delta = mul(adj(li), li);            // (P^H W)^-1
+        HIPCHK(upload(mul(delta, cm), h_dc, d_dc));
+        HIPCHK(upload(delta, h_dl, d_dl));
+        HIPCHK(launch_block_update(g, fmt, s, X, &X, P, 1.0, d_dc, nullptr, nullptr, c.st));
+        if (normal) HIPCHK(launch_block_update(g, fmt, s, S, &S, MP, -1.0, d_dc, w.upart, w.sc.ss, c.st));
+        HIPCHK(launch_block_update(g, fmt, s, Q, &Q, W, -1.0, d_dl, nullptr, nullptr, c.st));
+        HIPCHK(gram(Q, Q, gm));
+        res->iters = it;
+        if (!cholesky(gm, l, rank_eps)) { res->breakdown = 1; break; }
+        const Mat psi = adj(l);
+        cm = mul(psi, cm);
+        if (converged()) break;
+        HIPCHK(upload(adj(lower_inv(l)), h_pi, d_pi));  // psi^-1 = (L^-1)^H
+        HIPCHK(upload(l, h_ph, d_ph));                   // psi^H = L
+        HIPCHK(launch_block_update(g, fmt, s, Q, nullptr, Q, 1.0, d_pi, nullptr, nullptr, c.st));
+        HIPCHK(launch_block_update(g, fmt, s, P, &Q, P, 1.0, d_ph, nullptr, nullptr, c.st));
+    }
+    HIPCHK(hipStreamSynchronize(c.st));
+    return WEO_OK;
+}
+
 // One precision level with the requested method.
 int run_method(Ctx& c, const Workspace& w, int method, int op, int fmt_op, int fmt_acc, const void* u,
                void* x_acc, int nrhs, double tol, int maxiter, int check_every, LevelResult* res) {
     if (method == WEO_SOLVER_BICGSTAB)
         return run_level_bicg(c, w, op, fmt_op, fmt_acc, u, x_acc, nrhs, tol, maxiter, check_every, res);
+    if (method == WEO_SOLVER_BLOCK_CG) return run_level_block(c, w, op, fmt_op, u, x_acc, nrhs, tol, maxiter, res);
     return run_level(c, w, op, fmt_op, fmt_acc, u, x_acc, nrhs, tol, maxiter, check_every, res);
 }
 
@@ -485,7 +710,8 @@ int check_params(const weo_solver_params* p, int fmt, int* inner_fmt) {
     if (!(p->tol > 0.0) || !std::isfinite(p->tol) || p->maxiter < 0) return WEO_ERR_ARG;
     if (p->check_every < 1 || (p->x0_given != 0 && p->x0_given != 1)) return WEO_ERR_ARG;
     if (p->mixed != 0 && p->mixed != 1) return WEO_ERR_ARG;
-    if (p->method != WEO_SOLVER_CG && p->method != WEO_SOLVER_BICGSTAB) return WEO_ERR_ARG;
+    if (p->method != WEO_SOLVER_CG && p->method != WEO_SOLVER_BICGSTAB && p->method != WEO_SOLVER_BLOCK_CG)
+        return WEO_ERR_ARG;
     // site blocks: the even-odd operator only; the inner level needs its own
     if ((p->clover || p->clover_inner) && p->op == WEO_OP_DW) return WEO_ERR_ARG;
     if (p->mixed && (p->clover != nullptr) != (p->clover_inner != nullptr)) return WEO_ERR_ARG;
@@ -496,6 +722,8 @@ int check_params(const weo_solver_params* p, int fmt, int* inner_fmt) {
         if (rc != WEO_OK) return rc;
         const int sp = fmt_info(*inner_fmt).spinor_prec;
         if (sp == WEO_F64) return WEO_ERR_FORMAT;
+        // block CG keeps every vector in one format: FP32 inner spinors
+        if (p->method == WEO_SOLVER_BLOCK_CG && sp != WEO_F32) return WEO_ERR_FORMAT;
         if (!(p->inner_tol > 0.0) || !(p->inner_tol < 1.0) || p->max_outer < 1) return WEO_ERR_ARG;
     } else {
         // a plain solve accumulates in its own format; FP16/BF16 storage is

@@ -156,6 +156,28 @@ hipError_t launch_bi_p(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const B
 hipError_t launch_bi_scalars(int kind, const BiScalHost& h, int nb, const double* pa, const double* pb,
                              const double* pc, hipStream_t st);
 
+// ---- block CG: Gram matrices and block updates --------------------------------
+// A block is s <= kMaxBlock fields of one format; column j is the field at
+// base + col[j] * stride.  FP64 and FP32 spinor formats only.
+constexpr int kMaxBlock = 16;
+constexpr int kGramStride = 2 * kMaxBlock * kMaxBlock;   // doubles per Gram partial
+struct BlockRef {
+    uint8_t* base;
+    uint64_t stride;
+    uint8_t col[kMaxBlock];
+};
+int block_gram_wg(const Geom& g, int fmt);      // Gram partials (each kGramStride doubles)
+int block_update_wg(const Geom& g, int fmt);    // norm partials per column of an update
+// out[(j s + k) 2 + {re, im}] = <a_j, b_k> (FP64 accumulation, deterministic)
+hipError_t launch_block_gram(const Geom& g, int fmt, int s, const BlockRef& a, const BlockRef& b, double* part,
+                             double* out, hipStream_t st);
+// out_j = [in0_j] + a sum_k in1_k T[k][j], T complex s x s row-major (re, im);
+// out may be in0 or in1.  nrm (optional, with npart scratch of
+// s * block_update_wg doubles): nrm[j] = ||out_j||^2.
+hipError_t launch_block_update(const Geom& g, int fmt, int s, const BlockRef& out, const BlockRef* in0,
+                               const BlockRef& in1, double a, const double* T, double* npart, double* nrm,
+                               hipStream_t st);
+
 // ---- pack / unpack --------------------------------------------------------
 hipError_t launch_pack_gauge(const Geom& g, int fmt, const void* canon, int canon_f64,
                              void* packed, hipStream_t s);

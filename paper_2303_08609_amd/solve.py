@@ -19,14 +19,15 @@ from .ops import Format, Lattice, _ptr, _stream
 OPS = {"M": W.WEO_OP_M, "MdagM": W.WEO_OP_MDAGM, "DW": W.WEO_OP_DW}
 
 
-METHODS = {"cg": W.WEO_SOLVER_CG, "bicgstab": W.WEO_SOLVER_BICGSTAB}
+METHODS = {"cg": W.WEO_SOLVER_CG, "bicgstab": W.WEO_SOLVER_BICGSTAB, "blockcg": W.WEO_SOLVER_BLOCK_CG}
 
 
 def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000, x0=None,
        inner: Format | None = None, u_inner=None, inner_tol=1e-3, max_outer=100,
        check_every=10, out=None, method="cg", clover=None, clover_inner=None):
     """Returns (x, info dict).  ``inner`` switches on FP64 defect correction;
-    ``method`` "cg" (CGLS / CG) or "bicgstab" (also for the inner solves);
+    ``method`` "cg" (CGLS / CG), "bicgstab" or "blockcg" (also for the inner
+    solves);
     ``clover`` / ``clover_inner``: packed inverse site blocks (clover-type M)."""
     p = W.weo_solver_params()
     p.op = OPS[op]

@@ -26,7 +26,7 @@ WEO_F64, WEO_F32, WEO_F16, WEO_BF16 = 0, 1, 2, 3
 WEO_LINK18, WEO_LINK12 = 0, 1
 WEO_MAX_RHS = 16
 WEO_OP_M, WEO_OP_MDAGM, WEO_OP_DW = 0, 1, 2
-WEO_SOLVER_CG, WEO_SOLVER_BICGSTAB = 0, 1
+WEO_SOLVER_CG, WEO_SOLVER_BICGSTAB, WEO_SOLVER_BLOCK_CG = 0, 1, 2
 WEO_FORCE_PROJECT, WEO_FORCE_ACCUMULATE = 1, 2
 
 

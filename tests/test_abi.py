@@ -158,3 +158,28 @@ def test_clover_sizes_and_validation_without_gpu():
     assert W.wilson_eo_clover_hop(lat, f, 1, 0, a, b, c, None, float("nan"), d, 1, None) == W.WEO_ERR_ARG
     assert W.wilson_eo_clover_apply(lat, f, 0, a, b, c, c, d, 1, None) == W.WEO_ERR_ARG       # in == out
     assert W.wilson_eo_clover_apply(lat, f, 0, a, None, c, d, b, 1, None) == W.WEO_ERR_ARG
+
+
+def test_block_cg_parameters_without_gpu():
+    """The block method's workspace: every level vector plus its Gram and
+    update partials; FP64 or FP32 vectors only (FP32 inner for a mixed solve)."""
+    lat = W.make_lattice((8, 8, 8, 16), 0.126)
+    f64, f32 = W.make_format(W.WEO_F64), W.make_format(W.WEO_F32)
+
+    def params(method, nrhs=12, mixed=0, inner=None, op=W.WEO_OP_M):
+        p = W.weo_solver_params()
+        p.op, p.nrhs, p.tol, p.maxiter, p.check_every = op, nrhs, 1e-10, 100, 10
+        p.mixed, p.inner_tol, p.max_outer, p.method = mixed, 1e-3, 10, method
+        if inner is not None:
+            p.inner = inner
+        return p
+    cg_b = W.wilson_eo_cg_workspace_bytes(lat, f64, params(W.WEO_SOLVER_CG))
+    blk = W.wilson_eo_cg_workspace_bytes(lat, f64, params(W.WEO_SOLVER_BLOCK_CG))
+    assert cg_b > 0 and blk > cg_b
+    for op in (W.WEO_OP_M, W.WEO_OP_MDAGM, W.WEO_OP_DW):
+        assert W.wilson_eo_cg_workspace_bytes(lat, f32, params(W.WEO_SOLVER_BLOCK_CG, op=op)) > 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(W.WEO_SOLVER_BLOCK_CG, mixed=1, inner=f32)) > 0
+    f16 = W.make_format(W.WEO_F16, W.WEO_F16, W.WEO_LINK12)
+    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(W.WEO_SOLVER_BLOCK_CG, mixed=1, inner=f16)) == 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(W.WEO_SOLVER_CG, mixed=1, inner=f16)) > 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(3)) == 0
