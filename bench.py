@@ -129,7 +129,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-solve", action="store_true",
                     help="short fixed run for rocprofv3: the 12-source 32^3x64 solve to 1e-10 "
-                         "(FP64 defect correction around FP16/12 BiCGStab), once to tune, once more")
+                         "(FP64 defect correction around --solve-inner / --solve-method inner "
+                         "solves), once to tune, once more")
+    ap.add_argument("--solve-inner", default="f16/f16/12", help="inner format of --profile-solve")
+    ap.add_argument("--solve-method", default="bicgstab", choices=["cg", "bicgstab", "blockcg"],
+                    help="inner method of --profile-solve")
     ap.add_argument("--profile-mode", action="store_true",
                     help="short fixed run for rocprofv3: a 1 GiB device copy (counter "
                          "calibration) and --steps hop launches per format, nothing else")
@@ -148,12 +152,13 @@ def main():
         from paper_2303_08609_amd.solve import cg
         lat12 = Lattice(DIMS, KAPPA, (1, 1, 1, -1))
         ud = to_device(inputs.gen_gauge(DIMS, EPS, 401))
-        f64, fi = Format("f64", "f64", 18), Format("f16", "f16", 12)
+        f64, fi = Format("f64", "f64", 18), Format(*parse_fmt(a.solve_inner))
         u64, ui = lat12.pack_gauge(ud, f64), lat12.pack_gauge(ud, fi)
         b12 = lat12.pack_spinor(to_device(inputs.gen_point_noise_sources(DIMS, 406)), f64)
         for k in range(2):
-            x, info = cg(lat12, f64, u64, b12, nrhs=12, tol=1e-10, inner=fi, u_inner=ui, inner_tol=1e-3,
-                         maxiter=50000, max_outer=100, method="bicgstab")
+            x, info = cg(lat12, f64, u64, b12, nrhs=12, tol=1e-10, inner=fi, u_inner=ui,
+                         inner_tol=1e-5 if a.solve_inner.startswith("f32") else 1e-3,
+                         maxiter=50000, max_outer=100, method=a.solve_method)
             torch.cuda.synchronize()
             print(f"[bench] profiled 12-rhs solve {k}: {info['seconds']:.4f} s, inner {info['iters']}, "
                   f"outer {info['outer_iters']}", file=sys.stderr, flush=True)

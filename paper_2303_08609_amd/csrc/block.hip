@@ -7,11 +7,9 @@
 // FP64 complex per chunk.  Inner products and linear combinations of fields
 // act chunk by chunk, so these kernels never look at sites.
 //
-// Gram: one wavefront per workgroup.  Each pass stages 64 consecutive chunks
-// of every column of A and B in LDS; the lanes then split the s x s result
-// into 4 x 4 cells and the 64 chunks among groups of lanes, accumulating in
-// FP64.  Each workgroup writes one partial matrix; a second kernel sums the
-// partials in a fixed order (deterministic).
+// Gram matrices accumulate in FP64 (products of FP32 inputs are exact in
+// FP64); every workgroup writes one partial matrix and a second kernel sums
+// the partials in a fixed order (deterministic).
 #include <algorithm>
 
 #include "weo_device.h"
@@ -19,10 +17,10 @@
 
 namespace weo {
 
-static constexpr int kGramWG = 1024;      // workgroups of the Gram kernel (max)
-static constexpr int kUpdBlk = 256;       // lanes per workgroup of the update
-static constexpr int kUpdWG = 2048;       // workgroups of the update (max)
-static constexpr int kLdsPad = 65;        // row stride in chunks (bank spread)
+static constexpr int kGramWG = 2048;      // workgroups of the Gram kernel (max)
+static constexpr int kMaxCells = 10;      // 4 x 4 cells of the upper triangle of a 16 x 16 matrix
+static constexpr int kUpdBlk = 256;       // lanes per workgroup of the update kernels
+static constexpr int kUpdWG = 2048;       // workgroups of the update kernels (max)
 
 template <int SP> struct Chunk;
 template <> struct Chunk<P_F32> {
@@ -55,129 +53,135 @@ __device__ __forceinline__ const uint4* col_ptr(const BlockRef& r, int j) {
     return reinterpret_cast<const uint4*>(r.base + (uint64_t)r.col[j] * r.stride);
 }
 
-// part[blockIdx.x][(j s + k) 2 + {re, im}] = sum over this workgroup's chunks
-// of conj(a_j) b_k.  SAME: b is a (loaded once).
+// Column pointers of a block with constant indices (a runtime index into the
+// argument's col[] would place the argument in scratch memory).
+__device__ __forceinline__ const uint4* col_sel(const BlockRef& r, int j) {
+    int c = 0;
+#pragma unroll
+    for (int t = 0; t < kMaxBlock; ++t)
+        if (t == j) c = r.col[t];
+    return reinterpret_cast<const uint4*>(r.base + (uint64_t)c * r.stride);
+}
+
+// Partial Gram sums, one column of part per workgroup:
+//   part[((j s + k) 2 + {re, im}) nwg + blockIdx.x] = sum of conj(a_j) b_k
+// over this workgroup's chunks, for j <= k; zero below the diagonal (both
+// Gram matrices of block CG are Hermitian).  The upper triangle is cut into
+// 4 x 4 cells, one wavefront per cell: per step a wave streams 64 consecutive
+// chunks of its 4 a columns and 4 b columns (each column is read by the
+// waves of its row or column of cells; the repeats come from the L1 cache).
+// SAME: b is a.
 template <int SP, bool SAME>
-__global__ void __launch_bounds__(64) k_bgram(uint64_t nch, int s, BlockRef A, BlockRef B, double* part) {
+__global__ void __launch_bounds__(64 * kMaxCells) k_bgram(uint64_t nch, int s, BlockRef A, BlockRef B,
+                                                            double* part) {
     using K = Chunk<SP>;
     using R = typename K::R;
-    __shared__ uint4 la[kMaxBlock * kLdsPad];
-    __shared__ uint4 lb[SAME ? 1 : kMaxBlock * kLdsPad];
-    const uint4* lbp = SAME ? la : lb;
-    const int lane = threadIdx.x;
-    const int nb = (s + 3) >> 2, cells = nb * nb, ng = 64 / cells;
-    const int grp = lane / cells, cell = lane - grp * cells;
-    const int j0 = (cell / nb) * 4, k0 = (cell % nb) * 4;
+    const int nb = (s + 3) >> 2;
+    const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int jb = 0, rem = c;
+    while (rem >= nb - jb) { rem -= nb - jb; ++jb; }
+    const int j0 = 4 * jb, k0 = 4 * (jb + rem);
+    // columns past s read column s - 1 (always valid memory); the entries
+    // they produce are never stored
+    const uint4* pa[4];
+    const uint4* pb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        pa[r] = col_sel(A, j0 + r < s ? j0 + r : s - 1);
+        pb[r] = col_sel(SAME ? A : B, k0 + r < s ? k0 + r : s - 1);
+    }
     double acc[4][4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b][0] = acc[a][b][1] = 0.0;
-
-    for (uint64_t c0 = (uint64_t)blockIdx.x * 64; c0 < nch; c0 += (uint64_t)gridDim.x * 64) {
-        const uint64_t ch = c0 + (uint64_t)lane;
-        const bool in = ch < nch;
-#pragma unroll
-        for (int j = 0; j < kMaxBlock; ++j) {
-            if (j < s) {
-                la[j * kLdsPad + lane] = in ? col_ptr(A, j)[ch] : make_uint4(0, 0, 0, 0);
-                if constexpr (!SAME) lb[j * kLdsPad + lane] = in ? col_ptr(B, j)[ch] : make_uint4(0, 0, 0, 0);
-            }
-        }
-        __syncthreads();
-        if (grp < ng) {
-            for (int m = grp; m < 64; m += ng) {
-                cx<R> a[4][K::N], b[4][K::N];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    K::unpack(la[(j0 + q) * kLdsPad + m], a[q]);
-                    K::unpack(lbp[(k0 + q) * kLdsPad + m], b[q]);
-                }
-#pragma unroll
-                for (int e = 0; e < K::N; ++e)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const double ax = a[q][e].x, ay = a[q][e].y;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const double bx = b[r][e].x, by = b[r][e].y;
-                            acc[q][r][0] = fma(ax, bx, fma(ay, by, acc[q][r][0]));
-                            acc[q][r][1] = fma(ax, by, fma(-ay, bx, acc[q][r][1]));
-                        }
-                    }
-            }
-        }
-        __syncthreads();
-    }
-    // sum the lane groups in order (LDS reused as doubles: 64 lanes x 32)
-    double* red = reinterpret_cast<double*>(la);
-    static_assert(sizeof(la) >= 64 * 32 * sizeof(double), "LDS too small for the reduction");
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (uint64_t ch = (uint64_t)blockIdx.x * 64 + lane; ch < nch; ch += (uint64_t)gridDim.x * 64) {
+        cx<R> a[4][K::N], b[4][K::N];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            red[lane * 32 + (q * 4 + r) * 2] = acc[q][r][0];
-            red[lane * 32 + (q * 4 + r) * 2 + 1] = acc[q][r][1];
+            K::unpack(pa[r][ch], a[r]);
+            K::unpack(pb[r][ch], b[r]);
         }
-    __syncthreads();
-    if (lane < cells) {
-        double* out = part + (size_t)blockIdx.x * kGramStride;
-        for (int e = 0; e < 32; ++e) {
-            double v = 0.0;
-            for (int gi = 0; gi < ng; ++gi) v += red[(gi * cells + lane) * 32 + e];
-            const int q = (e >> 1) >> 2, r = (e >> 1) & 3;
-            const int j = j0 + q, k = k0 + r;
-            if (j < s && k < s) out[(j * s + k) * 2 + (e & 1)] = v;
-        }
+#pragma unroll
+        for (int e = 0; e < K::N; ++e)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double ax = a[r][e].x, ay = a[r][e].y;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double bx = b[t][e].x, by = b[t][e].y;
+                    acc[r][t][0] = fma(ax, bx, fma(ay, by, acc[r][t][0]));
+                    acc[r][t][1] = fma(ax, by, fma(-ay, bx, acc[r][t][1]));
+                }
+            }
+    }
+    const size_t nwg = gridDim.x;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                double v = acc[r][t][q];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                const int j = j0 + r, k = k0 + t;
+                if (lane == 0 && j < s && k < s) part[((size_t)(j * s + k) * 2 + q) * nwg + blockIdx.x] = j <= k ? v : 0.0;
+            }
+    // entries below the diagonal in cells off it belong to no wave
+    for (int t = threadIdx.x; t < 2 * s * s; t += blockDim.x) {
+        const int j = (t >> 1) / s, k = (t >> 1) % s;
+        if ((j >> 2) > (k >> 2)) part[(size_t)t * nwg + blockIdx.x] = 0.0;
     }
 }
 
-// out[t] = sum_w part[w][t] in order, t < 2 s^2
-__global__ void __launch_bounds__(512) k_bgram_reduce(const double* part, int nwg, int n, double* out) {
-    const int t = threadIdx.x;
-    if (t >= n) return;
-    double v = 0.0;
-    for (int w = 0; w < nwg; ++w) v += part[(size_t)w * kGramStride + t];
-    out[t] = v;
-}
-
-// out_j = [in0_j] + a sum_k in1_k T[k][j]   (j < s), chunk by chunk.
-// out may be in0 or in1 (each lane reads all its chunks before it writes).
-// npart (optional): per-workgroup partials of ||out_j||^2, [j][gridDim.x].
-template <int SP, bool IN0, bool NORM>
-__global__ void __launch_bounds__(kUpdBlk) k_bupdate(uint64_t nch, int s, BlockRef out, BlockRef in0,
+// out_j = [in0_j] + a sum_k in1_k T[k][j]   (j < s), chunk by chunk: one
+// lane per chunk holds the chunk of every column in registers (NB >= s, a
+// multiple of 4, sizes the arrays) and reads all of them before it writes,
+// so out may be in0 or in1.  npart (optional): per-workgroup partials of
+// ||out_j||^2, [j][gridDim.x].
+template <int SP, int NB, bool EXACT, bool IN0, bool NORM>
+__global__ void __launch_bounds__(kUpdBlk) k_bupdate(uint64_t nch, int s_arg, BlockRef out, BlockRef in0,
                                                        BlockRef in1, double a, const double* T, double* npart) {
     using K = Chunk<SP>;
     using R = typename K::R;
-    __shared__ cx<R> t[kMaxBlock * kMaxBlock];
+    const int s = EXACT ? NB : s_arg;        // EXACT: the block size is NB
+    __shared__ cx<R> t[NB * NB];
     for (int i = threadIdx.x; i < s * s; i += blockDim.x) {
-        t[i].x = (R)(a * T[2 * i]);
-        t[i].y = (R)(a * T[2 * i + 1]);
+        t[(i / s) * NB + i % s].x = (R)(a * T[2 * i]);
+        t[(i / s) * NB + i % s].y = (R)(a * T[2 * i + 1]);
     }
     __syncthreads();
-    double nrm[kMaxBlock];
+    double nrm[NORM ? NB : 1];
 #pragma unroll
-    for (int j = 0; j < kMaxBlock; ++j) nrm[j] = 0.0;
+    for (int j = 0; j < (NORM ? NB : 1); ++j) nrm[j] = 0.0;
     for (uint64_t ch = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ch < nch;
          ch += (uint64_t)gridDim.x * blockDim.x) {
-        cx<R> v[kMaxBlock][K::N];
+        // keep the factor in LDS where hoisting it out of the loop spills or
+        // measured slower (FP64, the 16-wide bucket, the norm variant)
+        if constexpr (SP == P_F64 || NB > 12 || NORM) __asm__ volatile("" ::: "memory");
+        cx<R> v[NB][K::N], y[IN0 ? NB : 1][K::N];
 #pragma unroll
-        for (int k = 0; k < kMaxBlock; ++k)
+        for (int k = 0; k < NB; ++k)
             if (k < s) K::unpack(col_ptr(in1, k)[ch], v[k]);
+        if constexpr (IN0) {
 #pragma unroll
-        for (int j = 0; j < kMaxBlock; ++j) {
+            for (int j = 0; j < NB; ++j)
+                if (j < s) K::unpack(col_ptr(in0, j)[ch], y[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
             if (j < s) {
                 cx<R> o[K::N];
-                if constexpr (IN0) {
-                    K::unpack(col_ptr(in0, j)[ch], o);
-                } else {
 #pragma unroll
-                    for (int e = 0; e < K::N; ++e) o[e].x = o[e].y = R(0);
+                for (int e = 0; e < K::N; ++e) {
+                    if constexpr (IN0) o[e] = y[j][e];
+                    else o[e].x = o[e].y = R(0);
                 }
 #pragma unroll
-                for (int k = 0; k < kMaxBlock; ++k) {
+                for (int k = 0; k < NB; ++k) {
                     if (k < s) {
-                        const cx<R> tk = t[k * s + j];
+                        const cx<R> tk = t[k * NB + j];
 #pragma unroll
                         for (int e = 0; e < K::N; ++e) o[e] = fma_(v[k][e], tk, o[e]);
                     }
@@ -194,7 +198,7 @@ __global__ void __launch_bounds__(kUpdBlk) k_bupdate(uint64_t nch, int s, BlockR
     if constexpr (NORM) {
         __shared__ double wsum[kUpdBlk / 64];
 #pragma unroll
-        for (int j = 0; j < kMaxBlock; ++j) {
+        for (int j = 0; j < NB; ++j) {
             if (j < s) {
                 double v = nrm[j];
 #pragma unroll
@@ -212,14 +216,69 @@ __global__ void __launch_bounds__(kUpdBlk) k_bupdate(uint64_t nch, int s, BlockR
     }
 }
 
+// The last step of a block CG iteration, in one pass (one lane per chunk,
+// NB as for k_bupdate):
+//   Q <- Q TA;   P <- Q + P TB   (the new Q)
+template <int SP, int NB, bool EXACT>
+__global__ void __launch_bounds__(kUpdBlk) k_bqp(uint64_t nch, int s_arg, BlockRef Q, BlockRef P, const double* TA,
+                                                   const double* TB) {
+    using K = Chunk<SP>;
+    using R = typename K::R;
+    const int s = EXACT ? NB : s_arg;
+    __shared__ cx<R> ta[NB * NB], tb[NB * NB];
+    for (int i = threadIdx.x; i < s * s; i += blockDim.x) {
+        const int d = (i / s) * NB + i % s;
+        ta[d].x = (R)TA[2 * i]; ta[d].y = (R)TA[2 * i + 1];
+        tb[d].x = (R)TB[2 * i]; tb[d].y = (R)TB[2 * i + 1];
+    }
+    __syncthreads();
+    for (uint64_t ch = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ch < nch;
+         ch += (uint64_t)gridDim.x * blockDim.x) {
+        __asm__ volatile("" ::: "memory");      // the factors stay in LDS (measured faster)
+        cx<R> vq[NB][K::N], vp[NB][K::N];
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (k < s) {
+                K::unpack(col_ptr(Q, k)[ch], vq[k]);
+                K::unpack(col_ptr(P, k)[ch], vp[k]);
+            }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (j < s) {
+                cx<R> oq[K::N], op[K::N];
+#pragma unroll
+                for (int e = 0; e < K::N; ++e) oq[e].x = oq[e].y = R(0);
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+                    if (k < s) {
+                        const cx<R> t = ta[k * NB + j];
+#pragma unroll
+                        for (int e = 0; e < K::N; ++e) oq[e] = fma_(vq[k][e], t, oq[e]);
+                    }
+#pragma unroll
+                for (int e = 0; e < K::N; ++e) op[e] = oq[e];
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+                    if (k < s) {
+                        const cx<R> t = tb[k * NB + j];
+#pragma unroll
+                        for (int e = 0; e < K::N; ++e) op[e] = fma_(vp[k][e], t, op[e]);
+                    }
+                *reinterpret_cast<uint4*>(Q.base + (uint64_t)Q.col[j] * Q.stride + ch * 16) = K::pack(oq);
+                *reinterpret_cast<uint4*>(P.base + (uint64_t)P.col[j] * P.stride + ch * 16) = K::pack(op);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host ----
 static uint64_t chunks(const Geom& g, int fmt) { return spinor_field_bytes(g, fmt) / 16; }
 
-int block_gram_wg(const Geom& g, int fmt) {
+int block_gram_wg(const Geom& g, int fmt) {          // 64 chunks per workgroup and step
     const uint64_t n = (chunks(g, fmt) + 63) / 64;
     return (int)(n < (uint64_t)kGramWG ? n : (uint64_t)kGramWG);
 }
-int block_update_wg(const Geom& g, int fmt) {
+int block_update_wg(const Geom& g, int fmt) {        // one chunk per lane and step
     const uint64_t n = (chunks(g, fmt) + kUpdBlk - 1) / kUpdBlk;
     return (int)(n < (uint64_t)kUpdWG ? n : (uint64_t)kUpdWG);
 }
@@ -229,33 +288,50 @@ hipError_t launch_block_gram(const Geom& g, int fmt, int s, const BlockRef& a, c
     if (s < 1 || s > kMaxBlock) return hipErrorInvalidValue;
     const uint64_t n = chunks(g, fmt);
     const int wg = block_gram_wg(g, fmt);
-    const bool same = a.base == b.base && a.stride == b.stride &&
-                      std::equal(a.col, a.col + s, b.col);
+    const bool same = a.base == b.base && a.stride == b.stride && std::equal(a.col, a.col + s, b.col);
+    const int nb = (s + 3) / 4;
+    const dim3 grid(wg), block(64 * nb * (nb + 1) / 2);
     switch (fmt_info(fmt).spinor_prec) {
         case P_F64:
-            if (same) hipLaunchKernelGGL((k_bgram<P_F64, true>), dim3(wg), dim3(64), 0, st, n, s, a, b, part);
-            else hipLaunchKernelGGL((k_bgram<P_F64, false>), dim3(wg), dim3(64), 0, st, n, s, a, b, part);
+            if (same) hipLaunchKernelGGL((k_bgram<P_F64, true>), grid, block, 0, st, n, s, a, b, part);
+            else hipLaunchKernelGGL((k_bgram<P_F64, false>), grid, block, 0, st, n, s, a, b, part);
             break;
         case P_F32:
-            if (same) hipLaunchKernelGGL((k_bgram<P_F32, true>), dim3(wg), dim3(64), 0, st, n, s, a, b, part);
-            else hipLaunchKernelGGL((k_bgram<P_F32, false>), dim3(wg), dim3(64), 0, st, n, s, a, b, part);
+            if (same) hipLaunchKernelGGL((k_bgram<P_F32, true>), grid, block, 0, st, n, s, a, b, part);
+            else hipLaunchKernelGGL((k_bgram<P_F32, false>), grid, block, 0, st, n, s, a, b, part);
             break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bgram_reduce, dim3(1), dim3(512), 0, st, part, wg, 2 * s * s, out);
-    return hipGetLastError();
+    return launch_reduce(part, wg, 2 * s * s, out, st);
+}
+
+template <int SP, int NB, bool EX>
+static void bupdate_ex(uint64_t n, int wg, int s, const BlockRef& out, const BlockRef* in0, const BlockRef& in1,
+                       double a, const double* T, double* npart, hipStream_t st) {
+    const BlockRef z = in0 ? *in0 : in1;
+    const dim3 grid(wg), block(kUpdBlk);
+    if (in0 && npart) hipLaunchKernelGGL((k_bupdate<SP, NB, EX, true, true>), grid, block, 0, st, n, s, out, z, in1, a, T, npart);
+    else if (in0) hipLaunchKernelGGL((k_bupdate<SP, NB, EX, true, false>), grid, block, 0, st, n, s, out, z, in1, a, T, npart);
+    else if (npart) hipLaunchKernelGGL((k_bupdate<SP, NB, EX, false, true>), grid, block, 0, st, n, s, out, z, in1, a, T, npart);
+    else hipLaunchKernelGGL((k_bupdate<SP, NB, EX, false, false>), grid, block, 0, st, n, s, out, z, in1, a, T, npart);
+}
+
+template <int SP, int NB>
+static void bupdate_nb(uint64_t n, int wg, int s, const BlockRef& out, const BlockRef* in0, const BlockRef& in1,
+                       double a, const double* T, double* npart, hipStream_t st) {
+    if (s == NB) bupdate_ex<SP, NB, true>(n, wg, s, out, in0, in1, a, T, npart, st);
+    else bupdate_ex<SP, NB, false>(n, wg, s, out, in0, in1, a, T, npart, st);
 }
 
 template <int SP>
 static void bupdate_sp(uint64_t n, int wg, int s, const BlockRef& out, const BlockRef* in0, const BlockRef& in1,
                        double a, const double* T, double* npart, hipStream_t st) {
-    const BlockRef z = in0 ? *in0 : in1;
-    if (in0 && npart) hipLaunchKernelGGL((k_bupdate<SP, true, true>), dim3(wg), dim3(kUpdBlk), 0, st, n, s, out, z, in1, a, T, npart);
-    else if (in0) hipLaunchKernelGGL((k_bupdate<SP, true, false>), dim3(wg), dim3(kUpdBlk), 0, st, n, s, out, z, in1, a, T, npart);
-    else if (npart) hipLaunchKernelGGL((k_bupdate<SP, false, true>), dim3(wg), dim3(kUpdBlk), 0, st, n, s, out, z, in1, a, T, npart);
-    else hipLaunchKernelGGL((k_bupdate<SP, false, false>), dim3(wg), dim3(kUpdBlk), 0, st, n, s, out, z, in1, a, T, npart);
+    if (s <= 4) bupdate_nb<SP, 4>(n, wg, s, out, in0, in1, a, T, npart, st);
+    else if (s <= 8) bupdate_nb<SP, 8>(n, wg, s, out, in0, in1, a, T, npart, st);
+    else if (s <= 12) bupdate_nb<SP, 12>(n, wg, s, out, in0, in1, a, T, npart, st);
+    else bupdate_nb<SP, 16>(n, wg, s, out, in0, in1, a, T, npart, st);
 }
 
 hipError_t launch_block_update(const Geom& g, int fmt, int s, const BlockRef& out, const BlockRef* in0,
@@ -273,6 +349,40 @@ hipError_t launch_block_update(const Geom& g, int fmt, int s, const BlockRef& ou
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !nrm) return e;
     return launch_reduce(npart, wg, s, nrm, st);
+}
+
+}  // namespace weo
+
+namespace weo {
+
+template <int SP, int NB>
+static void bqp_nb(uint64_t n, int wg, int s, const BlockRef& q, const BlockRef& p, const double* ta,
+                   const double* tb, hipStream_t st) {
+    const dim3 grid(wg), block(kUpdBlk);
+    if (s == NB) hipLaunchKernelGGL((k_bqp<SP, NB, true>), grid, block, 0, st, n, s, q, p, ta, tb);
+    else hipLaunchKernelGGL((k_bqp<SP, NB, false>), grid, block, 0, st, n, s, q, p, ta, tb);
+}
+
+template <int SP>
+static void bqp_sp(uint64_t n, int wg, int s, const BlockRef& q, const BlockRef& p, const double* ta,
+                   const double* tb, hipStream_t st) {
+    if (s <= 4) bqp_nb<SP, 4>(n, wg, s, q, p, ta, tb, st);
+    else if (s <= 8) bqp_nb<SP, 8>(n, wg, s, q, p, ta, tb, st);
+    else if (s <= 12) bqp_nb<SP, 12>(n, wg, s, q, p, ta, tb, st);
+    else bqp_nb<SP, 16>(n, wg, s, q, p, ta, tb, st);
+}
+
+hipError_t launch_block_qp(const Geom& g, int fmt, int s, const BlockRef& q, const BlockRef& p, const double* ta,
+                           const double* tb, hipStream_t st) {
+    if (s < 1 || s > kMaxBlock) return hipErrorInvalidValue;
+    const uint64_t n = chunks(g, fmt);
+    const int wg = block_update_wg(g, fmt);
+    switch (fmt_info(fmt).spinor_prec) {
+        case P_F64: bqp_sp<P_F64>(n, wg, s, q, p, ta, tb, st); break;
+        case P_F32: bqp_sp<P_F32>(n, wg, s, q, p, ta, tb, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace weo

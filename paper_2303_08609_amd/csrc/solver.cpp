@@ -484,15 +484,16 @@ Mat adj(const Mat& x) {
         for (int j = 0; j < x.n; ++j) z(i, j) = std::conj(x(j, i));
     return z;
 }
-// From the device layout (re, im interleaved, G[j][k] = <a_j, b_k>), made
-// exactly Hermitian.
+// The Hermitian matrix whose upper triangle the device computed (re, im
+// interleaved, G[j][k] = <a_j, b_k> for j <= k).
 Mat gram_from(const std::vector<double>& g, int n) {
-    Mat m(n);
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) m(i, j) = cplx(g[(i * n + j) * 2], g[(i * n + j) * 2 + 1]);
     Mat h(n);
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) h(i, j) = 0.5 * (m(i, j) + std::conj(m(j, i)));
+        for (int j = i; j < n; ++j) {
+            const cplx v(g[(i * n + j) * 2], i == j ? 0.0 : g[(i * n + j) * 2 + 1]);
+            h(i, j) = v;
+            h(j, i) = std::conj(v);
+        }
     return h;
 }
 // G = L L^H.  False unless every pivot exceeds rank_eps times its diagonal
@@ -606,19 +607,19 @@ int run_level_block(Ctx& c, const Workspace& w, int op, int fmt, const void* u, 
         return e;
     };
     HIPCHK(upload(Mat::eye(s), h_id, d_id));
-    // R_0 = S (M^dag M) or A^dag S, gathered into Q; ||S_j||^2 into ss
+    // R_0 = S (M^dag M) or A^dag S, gathered into W; ||S_j||^2 into ss
     if (normal) {
         HIPCHK(launch_block_update(g, fmt, s, MP, nullptr, S, 1.0, d_id, w.upart, w.sc.ss, c.st));
-        HIPCHK(apply_a(c, fmt, u, 1, w.t, w.r, w.tmp, s, nullptr));
+        HIPCHK(apply_a(c, fmt, u, 1, w.t, w.q, w.tmp, s, nullptr));
     } else {
-        HIPCHK(launch_block_update(g, fmt, s, Q, nullptr, S, 1.0, d_id, nullptr, nullptr, c.st));
+        HIPCHK(launch_block_update(g, fmt, s, W, nullptr, S, 1.0, d_id, nullptr, nullptr, c.st));
     }
     Mat gm(s), l(s);
-    HIPCHK(gram(Q, Q, gm));
+    HIPCHK(gram(W, W, gm));
     if (!cholesky(gm, l, rank_eps)) { res->breakdown = 1; return WEO_OK; }
     Mat cm = adj(l);                                   // C = psi_0 (R_0 = Q C)
     HIPCHK(upload(adj(lower_inv(l)), h_pi, d_pi));     // Q = R_0 psi_0^-1
-    HIPCHK(launch_block_update(g, fmt, s, Q, nullptr, Q, 1.0, d_pi, nullptr, nullptr, c.st));
+    HIPCHK(launch_block_update(g, fmt, s, Q, nullptr, W, 1.0, d_pi, nullptr, nullptr, c.st));
     HIPCHK(launch_block_update(g, fmt, s, P, nullptr, Q, 1.0, d_id, nullptr, nullptr, c.st));
     auto converged = [&]() {
         for (int j = 0; j < s; ++j) {
@@ -656,8 +657,7 @@ int run_level_block(Ctx& c, const Workspace& w, int op, int fmt, const void* u, 
         if (converged()) break;
         HIPCHK(upload(adj(lower_inv(l)), h_pi, d_pi));  // psi^-1 = (L^-1)^H
         HIPCHK(upload(l, h_ph, d_ph));                   // psi^H = L
-        HIPCHK(launch_block_update(g, fmt, s, Q, nullptr, Q, 1.0, d_pi, nullptr, nullptr, c.st));
-        HIPCHK(launch_block_update(g, fmt, s, P, &Q, P, 1.0, d_ph, nullptr, nullptr, c.st));
+        HIPCHK(launch_block_qp(g, fmt, s, Q, P, d_pi, d_ph, c.st));
     }
     HIPCHK(hipStreamSynchronize(c.st));
     return WEO_OK;

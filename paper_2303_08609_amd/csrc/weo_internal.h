@@ -160,15 +160,16 @@ hipError_t launch_bi_scalars(int kind, const BiScalHost& h, int nb, const double
 // A block is s <= kMaxBlock fields of one format; column j is the field at
 // base + col[j] * stride.  FP64 and FP32 spinor formats only.
 constexpr int kMaxBlock = 16;
-constexpr int kGramStride = 2 * kMaxBlock * kMaxBlock;   // doubles per Gram partial
+constexpr int kGramStride = 2 * kMaxBlock * kMaxBlock;   // doubles of one s x s complex matrix (max)
 struct BlockRef {
     uint8_t* base;
     uint64_t stride;
     uint8_t col[kMaxBlock];
 };
-int block_gram_wg(const Geom& g, int fmt);      // Gram partials (each kGramStride doubles)
+int block_gram_wg(const Geom& g, int fmt);      // Gram partials: kGramStride doubles each
 int block_update_wg(const Geom& g, int fmt);    // norm partials per column of an update
-// out[(j s + k) 2 + {re, im}] = <a_j, b_k> (FP64 accumulation, deterministic)
+// out[(j s + k) 2 + {re, im}] = <a_j, b_k> for j <= k, 0 below the diagonal
+// (FP64 accumulation, deterministic; both matrices of block CG are Hermitian)
 hipError_t launch_block_gram(const Geom& g, int fmt, int s, const BlockRef& a, const BlockRef& b, double* part,
                              double* out, hipStream_t st);
 // out_j = [in0_j] + a sum_k in1_k T[k][j], T complex s x s row-major (re, im);
@@ -177,6 +178,9 @@ hipError_t launch_block_gram(const Geom& g, int fmt, int s, const BlockRef& a, c
 hipError_t launch_block_update(const Geom& g, int fmt, int s, const BlockRef& out, const BlockRef* in0,
                                const BlockRef& in1, double a, const double* T, double* npart, double* nrm,
                                hipStream_t st);
+// q <- q TA;  p <- q + p TB (with the new q), in place, one pass
+hipError_t launch_block_qp(const Geom& g, int fmt, int s, const BlockRef& q, const BlockRef& p, const double* ta,
+                           const double* tb, hipStream_t st);
 
 // ---- pack / unpack --------------------------------------------------------
 hipError_t launch_pack_gauge(const Geom& g, int fmt, const void* canon, int canon_f64,

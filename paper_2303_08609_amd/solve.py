@@ -103,7 +103,10 @@ def bench_solves(lat: Lattice, u_np, psi_np, u_dev64, psi_dev64, reps=1):
               "bf16_f16link12": Format("bf16", "f16", 12), "f16_f16link12": Format("f16", "f16", 12)}
     for name, inner in inners.items():
         ui = lat.pack_gauge(u_dev64, inner)
-        for meth, tag in (("cg", ""), ("bicgstab", "_bicgstab")):
+        methods = [("cg", ""), ("bicgstab", "_bicgstab")]
+        if name.startswith("fp32"):
+            methods.append(("blockcg", "_blockcg"))        # FP32 vectors only
+        for meth, tag in methods:
             dt, info = timed(lambda: cg(lat, f64, u64, b64, tol=1e-10, maxiter=50000, inner=inner,
                                         u_inner=ui, inner_tol=1e-3 if not name.startswith("fp32") else 1e-5,
                                         max_outer=100, method=meth))
@@ -167,8 +170,8 @@ def bench_solves_12rhs(dims=(32, 32, 32, 64), kappa=0.126, eps=0.5, seed_gauge=4
       solves, one right-hand side after the other;
     * batched mixed path: the 12 sources in one solve, FP64 defect correction
       around batched inner solves with FP16 / BF16 spinors and FP16 12-real
-      links (inner tolerance 1e-3);
-    each by CGLS and by BiCGStab inner solves.
+      links (inner tolerance 1e-3), or FP32 spinors (1e-5);
+    each by CGLS and by BiCGStab inner solves, the FP32 ones also by block CG.
     Links are packed before timing; each timed path runs once untimed first
     (kernel loading, multi-rhs shape tuning)."""
     from . import inputs
