@@ -220,7 +220,10 @@ def bench_solves_12rhs(dims=(32, 32, 32, 64), kappa=0.126, eps=0.5, seed_gauge=4
                         ("fp32_link12", Format("f32", "f32", 12))):
         ui = lat.pack_gauge(ud, inner)
         tol_in = 1e-5 if name.startswith("fp32") else 1e-3
-        for meth, tag in (("cg", ""), ("bicgstab", "_bicgstab")):
+        methods = [("cg", ""), ("bicgstab", "_bicgstab")]
+        if name.startswith("fp32"):
+            methods.append(("blockcg", "_blockcg"))        # FP32 vectors only
+        for meth, tag in methods:
             cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=inner, u_inner=ui, inner_tol=tol_in,
                maxiter=50000, max_outer=100, method=meth)      # first call tunes the hop shapes
             dt, (x, info) = _timed(lambda: cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=inner,
