@@ -201,3 +201,33 @@ def test_block_cg_degenerate_cases():
     x2 = lat.unpack_spinor(x2_p, F64, nrhs=3).cpu().numpy()
     assert np.array_equal(x2[0], x[0]) and np.array_equal(x2[2], x[2])
     assert S.rel_resid(m, x2[1], b[1]) <= 1e-9
+
+
+@pytest.mark.parametrize("fmt_t,nrhs", [(("f64", "f64", 18), 16), (("f64", "f64", 12), 13), (("f32", "f32", 18), 16),
+                                        (("f32", "f32", 12), 7), (("f64", "f64", 18), 1)],
+                         ids=["f64-16", "f64l12-13", "f32-16", "f32l12-7", "f64-1"])
+def test_block_cg_every_kernel_bucket(fmt_t, nrhs):
+    """Block sizes in every compiled bucket of the block kernels (4, 8, 12,
+    16; exact and partial), FP64 and FP32 vectors: the iterate after 3 steps
+    equals the oracle's (M X = B through the normal equations).  Bars: FP64
+    1e-11; FP32 2e-5, since three steps of the recurrence build their s x s
+    factors from FP32 vectors (about 20 roundings of 6e-8 each, amplified by
+    the conditioning of the Gram matrices)."""
+    print(f"block cg bucket fmt={fmt_t} nrhs={nrhs}", flush=True)
+    from tests._helpers import link_as_stored
+    sp, lp, reals = fmt_t
+    fmt = Format(*fmt_t)
+    dims, kappa = (6, 4, 2, 6), 0.125
+    u = inputs.gen_gauge(dims, 0.4, 210)
+    b = inputs.gen_spinor_half(dims, 211, nrhs=nrhs)
+    lat = Lattice(dims, kappa, AP)
+    x_p, info = cg(lat, fmt, lat.pack_gauge(to_device(u), fmt), lat.pack_spinor(to_device(b), fmt), nrhs=nrhs,
+                   tol=1e-30, maxiter=3, method="blockcg")
+    assert info["iters"] == 3
+    ul = link_as_stored(u, lp, reals)
+    m, md = _ops(ul, kappa)
+    xo, _, _ = S.block_cg(None, list(ROUND[sp](b)), 1e-30, 3, apply_m=m, apply_mdag=md)
+    x = lat.unpack_spinor(x_p, fmt, nrhs=nrhs).cpu().numpy().reshape(nrhs, -1)
+    tol = 1e-11 if sp == "f64" else 2e-5
+    for j in range(nrhs):
+        assert rel_err(x[j], xo[j]) < tol, j
