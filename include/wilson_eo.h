@@ -332,7 +332,12 @@ size_t wilson_eo_cg_workspace_bytes(const weo_lattice* lat, const weo_format* fm
 /* Solve for nrhs right-hand sides b (packed, format fmt, even parity; full
  * fields for WEO_OP_DW) into x.
  * u holds the links in format fmt; u_inner the links in p->inner (mixed only,
- * else ignored).  Synchronises `stream` before returning. */
+ * else ignored).  Synchronises `stream` before returning.
+ * With WEO_SOLVER_BLOCK_CG the right-hand sides whose start does not already
+ * meet the tolerance form one block (the others are left as they are);
+ * info->iters counts block iterations; the block method needs FP64 or FP32
+ * spinors (else WEO_ERR_FORMAT) and ends with WEO_BREAKDOWN if the block
+ * loses rank. */
 int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt,
                  const weo_solver_params* p,
                  const void* u, const void* u_inner,
