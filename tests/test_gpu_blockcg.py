@@ -231,3 +231,36 @@ def test_block_cg_every_kernel_bucket(fmt_t, nrhs):
     tol = 1e-11 if sp == "f64" else 2e-5
     for j in range(nrhs):
         assert rel_err(x[j], xo[j]) < tol, j
+
+
+@pytest.mark.parametrize("inner,method", [(("f16", "f16", 12), "bicgstab"), (("f32", "f32", 12), "blockcg")],
+                         ids=["f16l12-bicgstab", "f32l12-blockcg"])
+def test_twelve_source_solve_32_3x64_sampled(inner, method):
+    """The benchmark's 12-source solves at full size (32^3x64, point + noise
+    sources, links exp(0.5 i H), FP64 defect correction to 1e-10): the
+    library's FP64 true residuals meet the tolerance, and the oracle's M x at
+    sampled sites (faces, corners, the source's neighbours, random) differs
+    from b there by no more than the residual bound allows."""
+    print(f"12-source solve 32^3x64 inner={inner} method={method}", flush=True)
+    from tests.test_gpu_apply import _sample_sites
+    dims, kappa = (32, 32, 32, 64), 0.126
+    lat = Lattice(dims, kappa, AP)
+    u = cached_gauge(dims, 0.5, 401)
+    b = inputs.gen_point_noise_sources(dims, 406)
+    fi = Format(*inner)
+    ud = to_device(u)
+    x_p, info = cg(lat, F64, lat.pack_gauge(ud, F64), lat.pack_spinor(to_device(b), F64), nrhs=12, tol=1e-10,
+                   inner=fi, u_inner=lat.pack_gauge(ud, fi), inner_tol=1e-5 if inner[0] == "f32" else 1e-3,
+                   max_outer=100, maxiter=50000, method=method)
+    assert info["status"] == WE.WEO_OK, info
+    assert max(info["true_rel_resid"][:12]) <= 1e-10
+    x = lat.unpack_spinor(x_p, F64, nrhs=12).cpu().numpy().reshape(12, -1, 4, 3)
+    del x_p
+    sites = _sample_sites(dims, 12, 9)
+    for r in range(12):
+        xr = x[r].reshape(b[r].shape)
+        mx = W.apply_m_at_sites(u, xr, kappa, PH, sites)
+        br = b[r].reshape(-1, 4, 3)[sites]
+        assert np.linalg.norm(mx - br) <= 1e-10 * np.linalg.norm(b[r]), r
+        # and the sampled solution is not trivially small
+        assert np.linalg.norm(x[r][sites]) > 0.1 * np.linalg.norm(br)
