@@ -277,7 +277,9 @@ int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger,
                              without even-odd preconditioning (Sec. 2 compares
                              the two systems' condition); b and x hold nrhs
                              full fields, each the packed even half followed by
-                             the packed odd half (2 weo_spinor_bytes(.., 1)) */
+                             the packed odd half (2 weo_spinor_bytes(.., 1));
+                             single-precision-level solves only (mixed = 1 is
+                             WEO_ERR_ARG) */
 
 #define WEO_SOLVER_CG        0   /* CGLS for WEO_OP_M / WEO_OP_DW, CG for WEO_OP_MDAGM */
 #define WEO_SOLVER_BICGSTAB  1   /* BiCGStab (van der Vorst 1992) on the operator itself:

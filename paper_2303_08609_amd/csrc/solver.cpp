@@ -712,6 +712,10 @@ int check_params(const weo_solver_params* p, int fmt, int* inner_fmt) {
     if (p->mixed != 0 && p->mixed != 1) return WEO_ERR_ARG;
     if (p->method != WEO_SOLVER_CG && p->method != WEO_SOLVER_BICGSTAB && p->method != WEO_SOLVER_BLOCK_CG)
         return WEO_ERR_ARG;
+    // D_W: one precision level only.  Its full fields are handled as one
+    // packed field over twice the sites, which is only consistent between
+    // vectors of one precision (a record's plane layout depends on it)
+    if (p->op == WEO_OP_DW && p->mixed) return WEO_ERR_ARG;
     // site blocks: the even-odd operator only; the inner level needs its own
     if ((p->clover || p->clover_inner) && p->op == WEO_OP_DW) return WEO_ERR_ARG;
     if (p->mixed && (p->clover != nullptr) != (p->clover_inner != nullptr)) return WEO_ERR_ARG;

@@ -183,3 +183,7 @@ def test_block_cg_parameters_without_gpu():
     assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(W.WEO_SOLVER_BLOCK_CG, mixed=1, inner=f16)) == 0
     assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(W.WEO_SOLVER_CG, mixed=1, inner=f16)) > 0
     assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(3)) == 0
+    # D_W solves run at one precision level
+    for m in (W.WEO_SOLVER_CG, W.WEO_SOLVER_BICGSTAB, W.WEO_SOLVER_BLOCK_CG):
+        assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(m, mixed=1, inner=f32, op=W.WEO_OP_DW)) == 0
+        assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(m, op=W.WEO_OP_DW)) > 0

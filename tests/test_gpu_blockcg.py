@@ -6,6 +6,7 @@ inner solves, clover-type blocks, twelve point sources, and the degenerate
 cases (rank-deficient block, zero source, converged start)."""
 import numpy as np
 import pytest
+import torch
 
 from oracle import solvers as S
 from oracle import wilson as W
@@ -264,3 +265,28 @@ def test_twelve_source_solve_32_3x64_sampled(inner, method):
         assert np.linalg.norm(mx - br) <= 1e-10 * np.linalg.norm(b[r]), r
         # and the sampled solution is not trivially small
         assert np.linalg.norm(x[r][sites]) > 0.1 * np.linalg.norm(br)
+
+
+def test_block_cg_mixed_mdagm_and_dw_rejected():
+    """FP64 defect correction around FP32 block inner solves for M^dag M X = B
+    (4 sources) to 1e-10 against the oracle's residuals; on D_W (full fields)
+    defect correction is refused with an argument error."""
+    print("block cg mixed MdagM; D_W mixed rejected", flush=True)
+    from tests.test_gpu_solver import _full_field
+    dims, kappa = (6, 4, 4, 8), 0.125
+    lat = Lattice(dims, kappa, AP)
+    u = inputs.gen_gauge(dims, 0.4, 220)
+    ud = to_device(u)
+    u64, u32 = lat.pack_gauge(ud, F64), lat.pack_gauge(ud, F32)
+    b = inputs.gen_spinor_half(dims, 221, nrhs=4)
+    x_p, info = cg(lat, F64, u64, lat.pack_spinor(to_device(b), F64), nrhs=4, op="MdagM", tol=1e-10, inner=F32,
+                   u_inner=u32, inner_tol=1e-5, max_outer=30, maxiter=5000, method="blockcg")
+    assert info["status"] == WE.WEO_OK, info
+    m, md = _ops(u, kappa)
+    x = lat.unpack_spinor(x_p, F64, nrhs=4).cpu().numpy()
+    for j in range(4):
+        assert S.rel_resid(lambda v: md(m(v)), x[j], b[j]) <= 1e-10, j
+    bf = _full_field(lat, F64, inputs.gen_spinor_full(dims, 222))
+    for meth in ("cg", "blockcg"):
+        with pytest.raises(WE.WilsonEOError):
+            cg(lat, F64, u64, bf, op="DW", tol=1e-10, inner=F32, u_inner=u32, maxiter=10, method=meth)
