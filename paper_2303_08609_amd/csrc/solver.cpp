@@ -584,6 +584,12 @@ int run_level_block(Ctx& c, const Workspace& w, int op, int fmt, const void* u, 
     // synchronisation that follows its last upload
     std::vector<double> h_id(kGramStride), h_dc(kGramStride), h_dl(kGramStride), h_pi(kGramStride),
         h_ph(kGramStride), gh(kGramStride), ssv(s);
+    // every exit (early error returns included) waits for the stream before
+    // the host buffers above go out of scope (their uploads are asynchronous)
+    struct SyncOnExit {
+        hipStream_t st;
+        ~SyncOnExit() { (void)hipStreamSynchronize(st); }
+    } sync_on_exit{c.st};
     double* d_id = w.tm;
     double* d_dc = w.tm + kGramStride;
     double* d_dl = w.tm + 2 * kGramStride;
