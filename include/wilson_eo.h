@@ -218,8 +218,8 @@ int wilson_eo_face_unpack(const weo_lattice* lat, const weo_format* fmt,
                           void* out, int nrhs, void* stream);
 
 /* ---- site-local diagonal blocks (clover-type D_ee, D_oo; Sec. 2) ----------
- * For the clover matrix D_ee and D_oo are site-local block-diagonal
- * operations (Sec. 2).  Here D = A - kappa H with A(x) a 12 x 12 Hermitian
+ * With a clover term the diagonal blocks of Eqs. (3)-(5) act site by site
+ * (Sec. 2).  Here D = A - kappa H with A(x) a 12 x 12 Hermitian
  * site matrix commuting with gamma5 (as 1 + c sigma_mu_nu F_mu_nu does), so
  * that D_eo = -kappa H_eo, D_oe = -kappa H_oe and A is given by two 6 x 6
  * Hermitian blocks in the gamma5 eigenbasis (gamma5 = -[[0,1],[1,0]] in 2 x 2

@@ -2,9 +2,8 @@
 
 Sec. 2 states the even-odd system for a general fermion matrix: Eq. (4),
 (1 - D_ee^-1 D_eo D_oo^-1 D_oe) xi_e = D_ee^-1 (eta_e - D_eo D_oo^-1 eta_o),
-and Eq. (5), xi_o = D_oo^-1 (eta_o - D_oe xi_e), and notes that for the clover
-matrix D_ee and D_oo are site-local block-diagonal operations (for Wilson they
-are the unit matrix).  Here D = A - kappa H with A(x) a site-local 12 x 12
+and Eq. (5), xi_o = D_oo^-1 (eta_o - D_oe xi_e); with a clover term its
+diagonal blocks act site by site, and for Wilson they are the unit matrix.  Here D = A - kappa H with A(x) a site-local 12 x 12
 matrix (spin x colour) that commutes with gamma5, as a clover term
 1 + c sigma_mu_nu F_mu_nu does.  D_eo = -kappa P_e H P_o, D_oe = -kappa P_o H P_e.
 
@@ -61,6 +60,45 @@ def apply_m_clover(u, psi_e, kappa, phases, ainv_e, ainv_o, dagger=False):
     ah_o = np.conj(np.swapaxes(ainv_o, -1, -2))
     t = apply_sites(ah_o, hop_eo(u, apply_sites(ah_e, psi_e), 0, phases, dagger=True))
     return psi_e - kappa * kappa * hop_eo(u, t, 1, phases, dagger=True)
+
+
+def apply_m_clover_at_sites(u, psi_e, kappa, phases, ainv_at, half_indices, dagger=False):
+    """(M psi_e) of ``apply_m_clover`` at the listed even half indices, for
+    lattices where whole-lattice site matrices are inconvenient: ``ainv_at(x,
+    y, z, t)`` returns the inverse site matrix [12, 12] of one site.  Each
+    output is psi_e(x) - kappa^2 A^-1(x) sum over the neighbours y of x of
+    H(x, y) A^-1(y) (H psi_e)(y) (the adjoint takes A^-dag and the adjoint
+    hops in the reverse order).  Returns (n, 4, 3)."""
+    from .lattice import half_index_coords
+    from .wilson import _half_getter, hop_at_site
+    lt, lz, ly, lxh = psi_e.shape[:4]
+    dims = (2 * lxh, ly, lz, lt)
+    get_e = _half_getter(psi_e, 0, dims)
+
+    def site_mat(site, v):
+        a = ainv_at(*site)
+        if dagger:
+            a = np.conj(a.T)
+        return (a @ v.reshape(12)).reshape(4, 3)
+
+    if dagger:
+        def get_src(x, y, z, t):
+            return site_mat((x, y, z, t), get_e(x, y, z, t))
+    else:
+        get_src = get_e
+
+    def get_mid(x, y, z, t):
+        return site_mat((x, y, z, t), hop_at_site(u, get_src, (x, y, z, t), phases, dims, dagger))
+
+    out = []
+    for ih in half_indices:
+        site = half_index_coords(dims, 0, int(ih))
+        x, y, z, t = site
+        hh = hop_at_site(u, get_mid, site, phases, dims, dagger)
+        if not dagger:
+            hh = site_mat(site, hh)
+        out.append(psi_e[t, z, y, x >> 1] - kappa * kappa * hh)
+    return np.array(out)
 
 
 def dense_sites(a12_full):

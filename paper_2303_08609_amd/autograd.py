@@ -7,7 +7,9 @@ the gradient g of z satisfies dL = Re sum conj(g) dz.
   g_psi = M^dag g_out = gamma5 M gamma5 g_out (one adjoint apply) and
   g_U from the link-gradient kernel with Lambda = (g_out, H_eo^dag g_out),
   R = (psi, H_oe psi) and coefficient -kappa^2.
-* ``wilson_solve(U, phi, lat)`` returns chi = (M^dag M)^-1 phi.  Backward:
+* ``wilson_solve(U, phi, lat)`` returns chi = (M^dag M)^-1 phi (with
+  mixed = True by FP64 defect correction around FP32 inner solves, also for
+  complex64 fields).  Backward:
   lambda = (M^dag M)^-1 g_chi (adjoint solve through the same CG), g_phi =
   lambda, and g_U = g[Re<-M lambda, M chi>] + g[Re<-M chi, M lambda>], each
   term a link-gradient kernel call.
@@ -19,6 +21,8 @@ one-parity spinors [Lt][Lz][Ly][Lx/2][4][3].  complex128 computes in FP64,
 complex64 in FP32 (18-real links).
 """
 from __future__ import annotations
+
+import warnings
 
 import torch
 
@@ -86,10 +90,7 @@ class WilsonSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u, phi, lat: Lattice, tol: float = 1e-12, mixed: bool = False):
         fmt = _fmt_for(phi)
-        u_p = lat.pack_gauge(u.contiguous(), fmt)
-        b_p = lat.pack_spinor(phi.contiguous(), fmt)
-        chi_p, info = _solve_normal(lat, fmt, u, u_p, b_p, tol, mixed)
-        chi = lat.unpack_spinor(chi_p, fmt, dtype=phi.dtype)
+        chi, info = _solve_canon(lat, u, phi, tol, mixed)
         ctx.save_for_backward(u, chi)
         ctx.lat, ctx.fmt, ctx.tol, ctx.mixed = lat, fmt, tol, mixed
         ctx.info = info
@@ -99,13 +100,13 @@ class WilsonSolve(torch.autograd.Function):
     def backward(ctx, g_chi):
         u, chi = ctx.saved_tensors
         lat, fmt = ctx.lat, ctx.fmt
-        u_p = lat.pack_gauge(u.contiguous(), fmt)
-        gb = lat.pack_spinor(g_chi.contiguous(), fmt)
-        lam_p, _ = _solve_normal(lat, fmt, u, u_p, gb, ctx.tol, ctx.mixed)
+        lam, _ = _solve_canon(lat, u, g_chi.to(chi.dtype), ctx.tol, ctx.mixed)
         g_u = g_phi = None
         if ctx.needs_input_grad[1]:
-            g_phi = lat.unpack_spinor(lam_p, fmt, dtype=chi.dtype)
+            g_phi = lam
         if ctx.needs_input_grad[0]:
+            u_p = lat.pack_gauge(u.contiguous(), fmt)
+            lam_p = lat.pack_spinor(lam, fmt)
             chi_p = lat.pack_spinor(chi.contiguous(), fmt)
             m_lam = lat.apply(u_p, lam_p, fmt)
             m_chi = lat.apply(u_p, chi_p, fmt)
@@ -117,13 +118,38 @@ class WilsonSolve(torch.autograd.Function):
         return g_u, g_phi, None, None, None
 
 
-def _solve_normal(lat, fmt, u_canon, u_p, b_p, tol, mixed):
-    if mixed and fmt.spinor == "f64":
-        inner = Format("f32", "f32", 18)
-        u_in = lat.pack_gauge(u_canon.contiguous(), inner)
-        return cg(lat, fmt, u_p, b_p, op="MdagM", tol=tol, inner=inner, u_inner=u_in,
-                  inner_tol=1e-5, maxiter=100000)
-    return cg(lat, fmt, u_p, b_p, op="MdagM", tol=tol, maxiter=100000)
+def _solve_canon(lat, u, b, tol, mixed, maxiter=100000):
+    """chi = (M^dag M)^-1 b for canonical fields; chi has b's dtype.
+    mixed = False: CG in the fields' own precision.  mixed = True: FP64 defect
+    correction around FP32 inner solves, whatever the fields' precision (FP32
+    fields are widened exactly), so that FP32 gradients rest on a solve
+    accurate to tol.  Raises WilsonEOError unless the solve reports WEO_OK: an
+    unconverged forward or adjoint solve would otherwise turn into silently
+    wrong values and gradients."""
+    fmt = Format("f64", "f64", 18) if mixed else _fmt_for(b)
+    u_p = lat.pack_gauge(u.contiguous(), fmt)
+    b_p = lat.pack_spinor(b.contiguous(), fmt)
+    x_p, info = _solve_normal(lat, fmt, u, u_p, b_p, tol, mixed, maxiter)
+    return lat.unpack_spinor(x_p, fmt, dtype=b.dtype), info
+
+
+def _solve_normal(lat, fmt, u_canon, u_p, b_p, tol, mixed, maxiter=100000):
+    """Packed chi = (M^dag M)^-1 b in format fmt (FP64 defect correction
+    around FP32 inner solves when mixed and fmt is FP64).  Raises
+    WilsonEOError unless the solve reports WEO_OK."""
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", W.SolverWarning)
+        if mixed and fmt.spinor == "f64":
+            inner = Format("f32", "f32", 18)
+            u_in = lat.pack_gauge(u_canon.contiguous(), inner)
+            x, info = cg(lat, fmt, u_p, b_p, op="MdagM", tol=tol, inner=inner, u_inner=u_in,
+                         inner_tol=1e-5, maxiter=maxiter)
+        else:
+            x, info = cg(lat, fmt, u_p, b_p, op="MdagM", tol=tol, maxiter=maxiter)
+    if info["status"] != W.WEO_OK:
+        raise W.WilsonEOError(info["status"], f"wilson_solve (true residual {info['true_rel_resid'][0]:.3e}, "
+                                              f"tolerance {tol:.1e})")
+    return x, info
 
 
 def wilson_apply(u, psi, lat: Lattice, dagger=False):

@@ -1,5 +1,5 @@
-// Site-local diagonal blocks of a clover-type operator (paper Sec. 2: for the
-// clover matrix D_ee and D_oo are site-local block-diagonal operations).
+// Site-local diagonal blocks of a clover-type operator: with a clover term the
+// diagonal blocks D_ee, D_oo of Eqs. (3)-(5) act site by site (Sec. 2).
 //
 // The site matrix commutes with gamma5, so in the gamma5 eigenbasis of the
 // Dirac representation (gamma5 = -[[0, 1], [1, 0]] in 2 x 2 spin blocks) it is

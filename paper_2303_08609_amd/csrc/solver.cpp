@@ -824,7 +824,8 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             return rc;
         for (int r = 0; r < n; ++r)
             if (!(info->true_rel_resid[r] <= p->tol)) status = WEO_NOT_CONVERGED;
-        if (lr.breakdown) status = WEO_BREAKDOWN;
+        // a breakdown matters only where a right-hand side is still unconverged
+        if (lr.breakdown && status != WEO_OK) status = WEO_BREAKDOWN;
     } else {
         // FP64 defect correction around inner solves in the inner format.
         const double target = 12.0 * (double)gb.vh;    // unit RMS per complex component

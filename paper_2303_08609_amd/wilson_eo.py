@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import warnings
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwilson_eo.so")
@@ -103,6 +104,11 @@ class WilsonEOError(RuntimeError):
         super().__init__(f"{where}: {strerror(code)} (code {code})")
 
 
+class SolverWarning(RuntimeWarning):
+    """A solve ended without meeting its tolerance (WEO_NOT_CONVERGED) or
+    broke down (WEO_BREAKDOWN); the returned x is the last iterate."""
+
+
 def load(path: str = LIB_PATH):
     """Load libwilson_eo.so and declare its signatures (idempotent)."""
     global _lib
@@ -128,8 +134,11 @@ def strerror(code: int) -> str:
 
 
 def check(code: int, where: str) -> int:
+    """Raise on a negative (error) code; warn on a positive solver status."""
     if code < 0:
         raise WilsonEOError(code, where)
+    if code > 0:
+        warnings.warn(f"{where}: {strerror(code)} (status {code})", SolverWarning, stacklevel=2)
     return code
 
 

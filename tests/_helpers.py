@@ -57,6 +57,28 @@ def rel_err(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def site_rel_max(a, b):
+    """Largest per-site relative error max_s ||a_s - b_s|| / ||b_s|| over the
+    12-component records of two spinor fields (any leading shape ending in
+    (4, 3)): a defect confined to a few sites is not diluted by the rest of
+    the field as it is in the norm-wise ``rel_err``."""
+    a = np.asarray(a).reshape(-1, 12)
+    b = np.asarray(b).reshape(-1, 12)
+    return float((np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)).max())
+
+
+def sample_sites(dims, n, seed):
+    """Half indices of sites on every face and corner of the lattice plus n
+    random ones (for checks at sampled sites on lattices too large for the
+    whole-field oracle)."""
+    lx, ly, lz, lt = dims
+    vh = lx * ly * lz * lt // 2
+    g = np.random.default_rng(seed)
+    corners = [0, lx // 2 - 1, vh - 1, vh - lx // 2, (lx // 2) * (ly - 1),
+               (lx // 2) * ly * (lz - 1), (lx // 2) * ly * lz * (lt - 1)]
+    return sorted(set(corners + [int(v) for v in g.integers(0, vh, n)]))
+
+
 _GAUGE_CACHE = {}
 
 

@@ -102,10 +102,34 @@ def test_argument_validation_without_gpu():
     assert W.weo_pack_gauge(lat, f, a, 0, None, None) == W.WEO_ERR_ARG
 
 
-def test_python_raises_on_error_codes():
+def test_python_raises_on_error_codes_and_warns_on_solver_status():
     with pytest.raises(W.WilsonEOError):
         W.check(W.WEO_ERR_ARG, "x")
-    assert W.check(W.WEO_NOT_CONVERGED, "x") == W.WEO_NOT_CONVERGED
+    for st in (W.WEO_NOT_CONVERGED, W.WEO_BREAKDOWN):
+        with pytest.warns(W.SolverWarning):
+            assert W.check(st, "x") == st
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        assert W.check(W.WEO_OK, "x") == W.WEO_OK
+
+
+def test_autograd_solve_raises_on_unconverged_status(monkeypatch):
+    """The autograd solve refuses a forward or adjoint solve that did not
+    converge (else its gradients would be silently wrong).  The solver
+    front end is replaced by one that reports WEO_NOT_CONVERGED, so no GPU is
+    needed."""
+    from paper_2303_08609_amd import autograd as AG
+    from paper_2303_08609_amd.ops import Format
+
+    def fake_cg(*args, **kw):
+        return None, {"status": W.WEO_NOT_CONVERGED, "true_rel_resid": [0.5]}
+    monkeypatch.setattr(AG, "cg", fake_cg)
+    with pytest.raises(W.WilsonEOError) as e:
+        AG._solve_normal(None, Format("f32", "f32", 18), None, None, None, 1e-10, False, maxiter=1)
+    assert e.value.code == W.WEO_NOT_CONVERGED
+    monkeypatch.setattr(AG, "cg", lambda *a, **k: ("x", {"status": W.WEO_OK, "true_rel_resid": [0.0]}))
+    assert AG._solve_normal(None, Format("f32", "f32", 18), None, None, None, 1e-10, False)[0] == "x"
 
 
 def test_face_sizes_and_validation_without_gpu():

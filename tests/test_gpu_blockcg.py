@@ -263,6 +263,11 @@ def test_twelve_source_solve_32_3x64_sampled(inner, method):
         mx = W.apply_m_at_sites(u, xr, kappa, PH, sites)
         br = b[r].reshape(-1, 4, 3)[sites]
         assert np.linalg.norm(mx - br) <= 1e-10 * np.linalg.norm(b[r]), r
+        # relative to b at the sampled sites themselves (the origin, where the
+        # point part of b sits, left out): the global relative residual 1e-10
+        # with room for an uneven spread over the sites
+        rest = [i for i, s in enumerate(sites) if s != 0]
+        assert np.linalg.norm((mx - br)[rest]) <= 2e-9 * np.linalg.norm(br[rest]), r
         # and the sampled solution is not trivially small
         assert np.linalg.norm(x[r][sites]) > 0.1 * np.linalg.norm(br)
 
