@@ -270,6 +270,22 @@ int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger,
                     const void* u, const void* in, void* out, void* tmp,
                     int nrhs, void* stream);
 
+/* ---- the operator without caller scratch ------------------------------------
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): wilson_eo_apply
+ * with its odd-parity intermediate field (tmp) held in a library-owned device
+ * array of WEO_NOALLOC_SCRATCH_BYTES per GPU, kept until the process ends.
+ * Allocates nothing.  Same arguments, results and launches as
+ * wilson_eo_apply; nrhs * weo_spinor_bytes(lat, fmt, 1) must not exceed
+ * WEO_NOALLOC_SCRATCH_BYTES (WEO_ERR_WORKSPACE otherwise; 128 MiB holds one
+ * FP32 field of 32^3x64).  The array is the current device's: a non-NULL
+ * stream must belong to the current device (WEO_ERR_ARG otherwise).  Every
+ * call on one GPU shares that GPU's array, so calls that overlap on one GPU
+ * (different streams or host threads) race; serialise them. */
+#define WEO_NOALLOC_SCRATCH_BYTES 134217728
+int wilson_eo_apply_noalloc(const weo_lattice* lat, const weo_format* fmt, int dagger,
+                            const void* u, const void* in, void* out, int nrhs, void* stream);
+
 /* ---- solvers (the paper names none; Sec. 2 says solves dominate) -------- */
 #define WEO_OP_M      0   /* solve M x = b by CGLS (CG on the normal equations) */
 #define WEO_OP_MDAGM  1   /* solve M^dag M x = b by CG */

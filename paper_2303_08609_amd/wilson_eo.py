@@ -26,6 +26,7 @@ WEO_BREAKDOWN = 2
 WEO_F64, WEO_F32, WEO_F16, WEO_BF16 = 0, 1, 2, 3
 WEO_LINK18, WEO_LINK12 = 0, 1
 WEO_MAX_RHS = 16
+WEO_NOALLOC_SCRATCH_BYTES = 134217728
 WEO_OP_M, WEO_OP_MDAGM, WEO_OP_DW = 0, 1, 2
 WEO_SOLVER_CG, WEO_SOLVER_BICGSTAB, WEO_SOLVER_BLOCK_CG = 0, 1, 2
 WEO_FORCE_PROJECT, WEO_FORCE_ACCUMULATE = 1, 2
@@ -87,6 +88,8 @@ _SIGS = {
                                          C.c_int, _vp]),
     "wilson_eo_apply": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, _vp, _vp, _vp,
                                   _vp, C.c_int, _vp]),
+    "wilson_eo_apply_noalloc": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, _vp, _vp, _vp,
+                                          C.c_int, _vp]),
     "wilson_eo_cg_workspace_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format),
                                                   _P(weo_solver_params)]),
     "wilson_eo_cg": (C.c_int, [_P(weo_lattice), _P(weo_format), _P(weo_solver_params), _vp, _vp,
@@ -168,6 +171,7 @@ weo_unpack_spinor = _call("weo_unpack_spinor")
 wilson_eo_hop = _call("wilson_eo_hop")
 wilson_eo_hop_axpy = _call("wilson_eo_hop_axpy")
 wilson_eo_apply = _call("wilson_eo_apply")
+wilson_eo_apply_noalloc = _call("wilson_eo_apply_noalloc")
 weo_clover_bytes = _call("weo_clover_bytes")
 weo_pack_clover = _call("weo_pack_clover")
 wilson_eo_clover_site = _call("wilson_eo_clover_site")

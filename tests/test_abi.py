@@ -211,3 +211,16 @@ def test_block_cg_parameters_without_gpu():
     for m in (W.WEO_SOLVER_CG, W.WEO_SOLVER_BICGSTAB, W.WEO_SOLVER_BLOCK_CG):
         assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(m, mixed=1, inner=f32, op=W.WEO_OP_DW)) == 0
         assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(m, op=W.WEO_OP_DW)) > 0
+
+
+def test_noalloc_apply_rejects_oversize_before_device_work():
+    """The no-allocation apply refuses an intermediate field larger than its
+    device array, and bad counts, before any HIP call (fake pointers)."""
+    # 32^3x64 FP64: 192 MiB per field, beyond the 128 MiB array
+    lat = W.make_lattice((32, 32, 32, 64), 0.126)
+    f64 = W.make_format(W.WEO_F64)
+    a, b, c = 1 << 28, 2 << 28, 3 << 28           # never touched: rejected first
+    assert W.wilson_eo_apply_noalloc(lat, f64, 0, a, b, c, 1, None) == W.WEO_ERR_WORKSPACE
+    f32 = W.make_format(W.WEO_F32)
+    assert W.wilson_eo_apply_noalloc(lat, f32, 0, a, b, c, 2, None) == W.WEO_ERR_WORKSPACE
+    assert W.wilson_eo_apply_noalloc(lat, f32, 0, a, b, c, 0, None) == W.WEO_ERR_ARG
