@@ -309,6 +309,46 @@ int wilson_eo_apply_noalloc(const weo_lattice* lat, const weo_format* fmt, int d
                                     only (a mixed solve needs FP32 inner spinors);
                                     WEO_BREAKDOWN when the block loses rank (e.g.
                                     two equal rhs) */
+#define WEO_SOLVER_SAP_GCR   3   /* flexible GCR (restart gcr_nkv) preconditioned by
+                                    the Schwarz alternating procedure (params sap),
+                                    WEO_OP_DW only; the right-hand sides are solved
+                                    one after the other.  The preconditioner runs in
+                                    FP32: with FP32 vectors on the solve's own links,
+                                    with FP64 vectors (mixed = 0) on u_inner in the
+                                    FP32 format `inner`.  info->iters sums the GCR
+                                    iterations over the right-hand sides */
+
+/* ---- Schwarz alternating procedure (QWS's preconditioner, Sec. 1-2) ---------
+ * The solver library the paper builds on preconditions its Krylov solver by
+ * the Schwarz alternating procedure on a domain-decomposed lattice.  Here:
+ * the lattice is cut into blocks of extent block[mu] (each dividing L_mu, with
+ * L_mu / block[mu] equal to 1 or even, at most 256 sites per block), coloured
+ * by the parity of the block coordinates.  One cycle sweeps the blocks of
+ * colour 0, then those of colour 1; a sweep solves every block's own Wilson
+ * system D_L e = r_L (D_W of Eq. (1) with the hops that leave the block
+ * dropped; where L_mu / block[mu] = 1 the hop across the lattice edge stays
+ * inside) by nmr minimal-residual steps started from zero, adds e to the
+ * solution and updates the residual.  ncy cycles from zero give psi = K eta,
+ * an approximation of D_W^-1 eta.  K is not linear (the MR step sizes depend
+ * on the data), so it preconditions flexible GCR. */
+typedef struct {
+    int block[4];   /* block extents (x, y, z, t) */
+    int ncy;        /* cycles, >= 1 */
+    int nmr;        /* MR steps per block solve, 1..64 */
+} weo_sap_params;
+
+/* Bytes of device workspace wilson_eo_sap needs (three sets of nrhs full
+ * fields: carried residual and the two colours' last block solutions). */
+size_t wilson_eo_sap_workspace_bytes(const weo_lattice* lat, const weo_format* fmt, int nrhs);
+
+/* psi = K eta for nrhs full fields (each the packed even half followed by the
+ * packed odd half, 2 weo_spinor_bytes(lat, fmt, 1) bytes).  fmt: FP32 spinors
+ * and FP32 links (18 or 12 reals), else WEO_ERR_FORMAT; invalid block extents,
+ * ncy or nmr: WEO_ERR_ARG.  eta, psi and the workspace must not overlap.
+ * Asynchronous on stream. */
+int wilson_eo_sap(const weo_lattice* lat, const weo_format* fmt, const weo_sap_params* sap,
+                  const void* u, const void* eta, void* psi, void* workspace, size_t ws_bytes,
+                  int nrhs, void* stream);
 
 typedef struct {
     int        op;          /* WEO_OP_M, WEO_OP_MDAGM or WEO_OP_DW */
@@ -332,6 +372,8 @@ typedef struct {
                                wilson_eo_clover_apply.  Not with WEO_OP_DW. */
     const void* clover_inner; /* the same blocks packed in format `inner` (mixed
                                only; required with clover) */
+    weo_sap_params sap;     /* WEO_SOLVER_SAP_GCR: the preconditioner */
+    int        gcr_nkv;     /* WEO_SOLVER_SAP_GCR: restart length, 1..16 */
 } weo_solver_params;
 
 typedef struct {

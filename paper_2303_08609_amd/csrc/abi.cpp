@@ -449,6 +449,52 @@ int wilson_eo_apply(const weo_lattice* lat, const weo_format* fmt, int dagger, c
     return hip_status(launch_hop(h, s));
 }
 
+// ---- Schwarz alternating procedure ------------------------------------------
+static int sap_checks(const weo_lattice* lat, const weo_format* fmt, int nrhs, Geom* g, int* id) {
+    WEO_TRY(check_lattice(lat, g));
+    WEO_TRY(check_fmt(fmt, id));
+    if (fmt_info(*id).spinor_prec != WEO_F32 || fmt_info(*id).link_prec != WEO_F32) return WEO_ERR_FORMAT;
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS) return WEO_ERR_ARG;
+    // full fields: both parities, per-lane offsets stay below 2^31 per plane
+    if ((uint64_t)g->vh > (1ull << 25)) return WEO_ERR_DIMS;
+    return WEO_OK;
+}
+
+static size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+size_t wilson_eo_sap_workspace_bytes(const weo_lattice* lat, const weo_format* fmt, int nrhs) {
+    Geom g;
+    int id;
+    if (sap_checks(lat, fmt, nrhs, &g, &id) != WEO_OK) return 0;
+    return 3 * round256((size_t)nrhs * 2 * spinor_field_bytes(g, id));
+}
+
+int wilson_eo_sap(const weo_lattice* lat, const weo_format* fmt, const weo_sap_params* sap, const void* u,
+                  const void* eta, void* psi, void* workspace, size_t ws_bytes, int nrhs, void* stream) {
+    Geom g;
+    int id;
+    WEO_TRY(sap_checks(lat, fmt, nrhs, &g, &id));
+    if (!sap || sap->ncy < 1 || sap->nmr < 1 || sap->nmr > 64) return WEO_ERR_ARG;
+    SapGeom sg;
+    if (make_sap_geom(g, sap->block, &sg) != 0) return WEO_ERR_ARG;
+    WEO_TRY(check_ptr(u));
+    WEO_TRY(check_ptr(eta));
+    WEO_TRY(check_ptr(psi));
+    if (!workspace) return WEO_ERR_WORKSPACE;
+    WEO_TRY(check_ptr(workspace));
+    const size_t nb = (size_t)nrhs * 2 * spinor_field_bytes(g, id), fb = round256(nb);
+    if (ws_bytes < 3 * fb) return WEO_ERR_WORKSPACE;
+    const size_t gb = gauge_field_bytes(g, id);
+    if (overlaps(eta, nb, psi, nb) || overlaps(workspace, 3 * fb, psi, nb) || overlaps(workspace, 3 * fb, eta, nb) ||
+        overlaps(u, gb, psi, nb) || overlaps(u, gb, workspace, 3 * fb))
+        return WEO_ERR_ARG;
+    double ph[4][2];
+    phases_of(lat, ph);
+    uint8_t* w = static_cast<uint8_t*>(workspace);
+    return hip_status(sap_apply(g, id, sg, sap->ncy, sap->nmr, lat->kappa, ph, u, eta, psi, w, w + fb, w + 2 * fb,
+                                nrhs, static_cast<hipStream_t>(stream)));
+}
+
 int wilson_eo_force(const weo_lattice* lat, const weo_format* fmt, const void* u, const void* lam_e,
                     const void* lam_o, const void* r_e, const void* r_o, double coeff, int flags,
                     void* g_canon, int canon_prec, void* stream) {

@@ -92,6 +92,9 @@ struct Workspace {
     void *r64, *t64, *tmp64;                              // outer (mixed) vectors
     double *pa, *pb, *pc;                                 // partial sums
     double *gpart, *upart, *gram, *tm;                    // block CG: partials, Gram, s x s factors
+    void *gphi[kGcrMax], *gchi[kGcrMax];                  // SAP-GCR: directions and their images
+    void *srho, *sd0, *sd1, *spin, *spout;                // SAP scratch; FP32 copies (FP64 level)
+    double *gcpart, *gcsum;                               // GCR partials and sums
     Scalars sc;
     size_t bytes;
 };
@@ -127,6 +130,25 @@ Workspace carve_ws(const Geom& g, int fmt, const weo_solver_params* p, int inner
     if (p->method == WEO_SOLVER_BICGSTAB) {
         w.rh = c.take(fo);
         w.s2 = c.take(fa);
+    }
+    if (p->method == WEO_SOLVER_SAP_GCR) {
+        // one right-hand side at a time: single fields of the level format and,
+        // for the preconditioner, of its FP32 format
+        const int pre = fmt_info(op).spinor_prec == WEO_F32 ? op : inner_fmt;
+        const size_t f1 = spinor_field_bytes(g, op), fp = spinor_field_bytes(g, pre);
+        for (int k = 0; k < p->gcr_nkv && k < kGcrMax; ++k) {
+            w.gphi[k] = c.take(f1);
+            w.gchi[k] = c.take(f1);
+        }
+        w.srho = c.take(fp);
+        w.sd0 = c.take(fp);
+        w.sd1 = c.take(fp);
+        if (pre != op) {
+            w.spin = c.take(fp);
+            w.spout = c.take(fp);
+        }
+        w.gcpart = static_cast<double*>(c.take((size_t)2 * kGcrMax * gcr_wg(g, op) * sizeof(double)));
+        w.gcsum = static_cast<double*>(c.take((size_t)2 * kGcrMax * sizeof(double)));
     }
     if (p->method == WEO_SOLVER_BLOCK_CG) {
         w.gpart = static_cast<double*>(c.take((size_t)block_gram_wg(g, op) * kGramStride * sizeof(double)));
@@ -166,6 +188,12 @@ struct Ctx {
     double ph[4][2];
     hipStream_t st;
     int applies;
+    // SAP-GCR: preconditioner blocks, cycles, MR steps, restart length, and
+    // the FP32 format and links the preconditioner runs on
+    SapGeom sap;
+    int ncy, nmr, nkv;
+    int fmt_pre;
+    const void* u_pre;
 };
 
 // out = A in with A = M (dagger 0) or M^dag (dagger 1); partial = ||out||^2.
@@ -669,12 +697,143 @@ int run_level_block(Ctx& c, const Workspace& w, int op, int fmt, const void* u, 
     return WEO_OK;
 }
 
+// Format conversion of nrhs solver vectors (scale per rhs, may be null).  A
+// full field (D_W) is two packed halves whose record planes depend on the
+// format, so it is converted half by half; one-parity fields in one pass.
+hipError_t convert_fields(Ctx& c, int fin, const void* in, int fout, void* out, int nrhs, const double* scale,
+                          int accumulate) {
+    if (!c.full) return launch_convert(c.gb, fin, in, fout, out, nrhs, scale, accumulate, c.st);
+    const size_t hi = spinor_field_bytes(c.g, fin), ho = spinor_field_bytes(c.g, fout);
+    for (int r = 0; r < nrhs; ++r)
+        for (int h = 0; h < 2; ++h) {
+            const size_t k = (size_t)2 * r + h;
+            const hipError_t e = launch_convert(c.g, fin, static_cast<const uint8_t*>(in) + k * hi, fout,
+                                                static_cast<uint8_t*>(out) + k * ho, 1, scale ? scale + r : nullptr,
+                                                accumulate, c.st);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+// Flexible GCR preconditioned by SAP, for D_W on full fields (op DW), one
+// right-hand side after the other.  Same contract as run_level: x_acc holds
+// the start, s_acc the residual b - D x (both in the level format fmt, the
+// residual updated in place), mask the live rhs, bb[r] = ||b||^2.  Per
+// iteration: phi_k = K r (SAP in FP32, converted when the level is FP64),
+// chi_k = D_W phi_k, classical Gram-Schmidt of chi_k against chi_0..k-1 (one
+// dot pass and one update pass that also gives ||chi_k||^2 and <chi_k, r>),
+// r -= c_k chi_k / ||chi_k||.  The chi_l are kept unnormalised with their
+// norms n_l on the host.  At the end of a cycle (nkv directions or
+// convergence) x += sum_k alpha_k phi_k from the upper-triangular system.
+int run_level_gcr(Ctx& c, const Workspace& w, int fmt, const void* u, void* x_acc, int nrhs, double tol,
+                  int maxiter, LevelResult* res) {
+    const Geom& gb = c.gb;
+    const size_t fb = spinor_field_bytes(gb, fmt);
+    const int nkv = c.nkv;
+    const uint32_t nwg = gcr_wg(gb, fmt);
+    const bool conv = c.fmt_pre != fmt;
+    res->iters = 0;
+    res->breakdown = 0;
+    std::vector<int> mask(nrhs);
+    std::vector<double> bb(nrhs);
+    HIPCHK(hipMemcpyAsync(mask.data(), w.sc.mask, nrhs * sizeof(int), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(bb.data(), w.sc.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    std::vector<double> sums(2 * kGcrMax);
+    auto fetch = [&](int nval) -> hipError_t {
+        hipError_t e = launch_reduce(w.gcpart, (int)nwg, nval, w.gcsum, c.st);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(sums.data(), w.gcsum, nval * sizeof(double), hipMemcpyDeviceToHost, c.st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(c.st);
+    };
+    const double tol2 = tol * tol;
+    for (int r = 0; r < nrhs; ++r) {
+        if (!mask[r]) continue;
+        uint8_t* rv = static_cast<uint8_t*>(w.s_acc) + (size_t)r * fb;
+        uint8_t* xv = static_cast<uint8_t*>(x_acc) + (size_t)r * fb;
+        // ||r||^2 of the start
+        {
+            const void* none[1] = {rv};
+            const double z = 0.0;
+            HIPCHK(launch_gcr_update(gb, fmt, 0, none, &z, &z, rv, nullptr, w.gcpart, c.st));
+            HIPCHK(fetch(1));
+        }
+        double rr = sums[0];
+        int it = 0;
+        bool breakdown = false;
+        while (!(rr <= tol2 * bb[r]) && it < maxiter && !breakdown) {
+            std::vector<std::complex<double>> a((size_t)nkv * nkv), cc(nkv);
+            std::vector<double> nrm(nkv);
+            int k = 0;
+            for (; k < nkv && it < maxiter; ++k) {
+                void* phi = w.gphi[k];
+                void* chi = w.gchi[k];
+                // phi_k = K r
+                if (conv) {
+                    HIPCHK(convert_fields(c, fmt, rv, c.fmt_pre, w.spin, 1, nullptr, 0));
+                    HIPCHK(sap_apply(c.g, c.fmt_pre, c.sap, c.ncy, c.nmr, c.lat->kappa, c.ph, c.u_pre, w.spin,
+                                     w.spout, w.srho, w.sd0, w.sd1, 1, c.st));
+                    HIPCHK(convert_fields(c, c.fmt_pre, w.spout, fmt, phi, 1, nullptr, 0));
+                } else {
+                    HIPCHK(sap_apply(c.g, fmt, c.sap, c.ncy, c.nmr, c.lat->kappa, c.ph, c.u_pre, rv, phi, w.srho,
+                                     w.sd0, w.sd1, 1, c.st));
+                }
+                // chi_k = D_W phi_k, orthogonalised against chi_0 .. chi_{k-1}
+                HIPCHK(apply_dw(c, fmt, u, 0, phi, chi, 1, nullptr));
+                std::vector<double> cre(kGcrMax, 0.0), cim(kGcrMax, 0.0);
+                if (k > 0) {
+                    HIPCHK(launch_gcr_dots(gb, fmt, k, w.gchi, chi, w.gcpart, c.st));
+                    HIPCHK(fetch(2 * k));
+                    for (int l = 0; l < k; ++l) {
+                        const std::complex<double> alk(sums[2 * l] / nrm[l], sums[2 * l + 1] / nrm[l]);
+                        a[(size_t)l * nkv + k] = alk;                  // <chi^_l, chi_k>
+                        cre[l] = -alk.real() / nrm[l];
+                        cim[l] = -alk.imag() / nrm[l];
+                    }
+                }
+                HIPCHK(launch_gcr_update(gb, fmt, k, w.gchi, cre.data(), cim.data(), chi, rv, w.gcpart, c.st));
+                HIPCHK(fetch(3));
+                nrm[k] = std::sqrt(sums[0]);
+                if (!(nrm[k] > 0.0) || !std::isfinite(nrm[k])) { breakdown = true; break; }
+                a[(size_t)k * nkv + k] = nrm[k];
+                cc[k] = std::complex<double>(sums[1], sums[2]) / nrm[k];     // <chi^_k, r>
+                // r -= c_k chi^_k, and ||r||^2
+                const double ur = -cc[k].real() / nrm[k], ui = -cc[k].imag() / nrm[k];
+                const void* one[1] = {chi};
+                HIPCHK(launch_gcr_update(gb, fmt, 1, one, &ur, &ui, rv, nullptr, w.gcpart, c.st));
+                HIPCHK(fetch(1));
+                rr = sums[0];
+                ++it;
+                if (rr <= tol2 * bb[r]) { ++k; break; }
+            }
+            // x += sum alpha_l phi_l with sum_{m >= l} a_lm alpha_m = c_l
+            std::vector<std::complex<double>> al(kGcrMax, 0.0);
+            for (int l = k - 1; l >= 0; --l) {
+                std::complex<double> t = cc[l];
+                for (int m = l + 1; m < k; ++m) t -= a[(size_t)l * nkv + m] * al[m];
+                al[l] = t / a[(size_t)l * nkv + l];
+            }
+            if (k > 0) {
+                std::vector<double> xr(kGcrMax), xi(kGcrMax);
+                for (int l = 0; l < k; ++l) { xr[l] = al[l].real(); xi[l] = al[l].imag(); }
+                HIPCHK(launch_gcr_update(gb, fmt, k, w.gphi, xr.data(), xi.data(), xv, nullptr, nullptr, c.st));
+            }
+        }
+        res->iters += it;
+        if (breakdown) res->breakdown = 1;
+    }
+    HIPCHK(hipStreamSynchronize(c.st));
+    return WEO_OK;
+}
+
 // One precision level with the requested method.
 int run_method(Ctx& c, const Workspace& w, int method, int op, int fmt_op, int fmt_acc, const void* u,
                void* x_acc, int nrhs, double tol, int maxiter, int check_every, LevelResult* res) {
     if (method == WEO_SOLVER_BICGSTAB)
         return run_level_bicg(c, w, op, fmt_op, fmt_acc, u, x_acc, nrhs, tol, maxiter, check_every, res);
     if (method == WEO_SOLVER_BLOCK_CG) return run_level_block(c, w, op, fmt_op, u, x_acc, nrhs, tol, maxiter, res);
+    if (method == WEO_SOLVER_SAP_GCR) return run_level_gcr(c, w, fmt_op, u, x_acc, nrhs, tol, maxiter, res);
     return run_level(c, w, op, fmt_op, fmt_acc, u, x_acc, nrhs, tol, maxiter, check_every, res);
 }
 
@@ -716,12 +875,13 @@ int check_params(const weo_solver_params* p, int fmt, int* inner_fmt) {
     if (!(p->tol > 0.0) || !std::isfinite(p->tol) || p->maxiter < 0) return WEO_ERR_ARG;
     if (p->check_every < 1 || (p->x0_given != 0 && p->x0_given != 1)) return WEO_ERR_ARG;
     if (p->mixed != 0 && p->mixed != 1) return WEO_ERR_ARG;
-    if (p->method != WEO_SOLVER_CG && p->method != WEO_SOLVER_BICGSTAB && p->method != WEO_SOLVER_BLOCK_CG)
+    if (p->method != WEO_SOLVER_CG && p->method != WEO_SOLVER_BICGSTAB && p->method != WEO_SOLVER_BLOCK_CG &&
+        p->method != WEO_SOLVER_SAP_GCR)
         return WEO_ERR_ARG;
-    // D_W: one precision level only.  Its full fields are handled as one
-    // packed field over twice the sites, which is only consistent between
-    // vectors of one precision (a record's plane layout depends on it)
-    if (p->op == WEO_OP_DW && p->mixed) return WEO_ERR_ARG;
+    if (p->method == WEO_SOLVER_SAP_GCR) {
+        if (p->op != WEO_OP_DW || p->gcr_nkv < 1 || p->gcr_nkv > kGcrMax) return WEO_ERR_ARG;
+        if (p->sap.ncy < 1 || p->sap.nmr < 1 || p->sap.nmr > 64) return WEO_ERR_ARG;
+    }
     // site blocks: the even-odd operator only; the inner level needs its own
     if ((p->clover || p->clover_inner) && p->op == WEO_OP_DW) return WEO_ERR_ARG;
     if (p->mixed && (p->clover != nullptr) != (p->clover_inner != nullptr)) return WEO_ERR_ARG;
@@ -732,14 +892,29 @@ int check_params(const weo_solver_params* p, int fmt, int* inner_fmt) {
         if (rc != WEO_OK) return rc;
         const int sp = fmt_info(*inner_fmt).spinor_prec;
         if (sp == WEO_F64) return WEO_ERR_FORMAT;
-        // block CG keeps every vector in one format: FP32 inner spinors
-        if (p->method == WEO_SOLVER_BLOCK_CG && sp != WEO_F32) return WEO_ERR_FORMAT;
+        // block CG keeps every vector in one format: FP32 inner spinors; a
+        // D_W level mixes the accumulation format (FP32) with the operator's
+        // only where their records coincide (FP32 inner spinors); the SAP
+        // preconditioner runs on FP32 spinors and links
+        if ((p->method == WEO_SOLVER_BLOCK_CG || p->op == WEO_OP_DW) && sp != WEO_F32) return WEO_ERR_FORMAT;
+        if (p->method == WEO_SOLVER_SAP_GCR && fmt_info(*inner_fmt).link_prec != WEO_F32) return WEO_ERR_FORMAT;
         if (!(p->inner_tol > 0.0) || !(p->inner_tol < 1.0) || p->max_outer < 1) return WEO_ERR_ARG;
     } else {
         // a plain solve accumulates in its own format; FP16/BF16 storage is
         // only used as the inner format of a mixed solve
         const int sp = fmt_info(fmt).spinor_prec;
         if (sp != WEO_F64 && sp != WEO_F32) return WEO_ERR_FORMAT;
+        if (p->method == WEO_SOLVER_SAP_GCR) {
+            if (sp == WEO_F32) {
+                if (fmt_info(fmt).link_prec != WEO_F32) return WEO_ERR_FORMAT;
+            } else {
+                // FP64 vectors: the preconditioner's FP32 format and links
+                const int rc = check_fmt(&p->inner, inner_fmt);
+                if (rc != WEO_OK) return rc;
+                if (fmt_info(*inner_fmt).spinor_prec != WEO_F32 || fmt_info(*inner_fmt).link_prec != WEO_F32)
+                    return WEO_ERR_FORMAT;
+            }
+        }
     }
     return WEO_OK;
 }
@@ -756,6 +931,8 @@ extern "C" size_t wilson_eo_cg_workspace_bytes(const weo_lattice* lat, const weo
     if (check_lattice(lat, &g) != WEO_OK || check_fmt(fmt, &id) != WEO_OK) return 0;
     if (check_params(p, id, &inner) != WEO_OK) return 0;
     if ((uint64_t)vector_geom(g, p->op).vh > (1ull << 26)) return 0;
+    SapGeom sg;
+    if (p->method == WEO_SOLVER_SAP_GCR && make_sap_geom(g, p->sap.block, &sg) != 0) return 0;
     return carve_ws(vector_geom(g, p->op), id, p, inner, nullptr, 0).bytes;
 }
 
@@ -772,7 +949,11 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
     if (!info) return WEO_ERR_ARG;
     if ((rc = check_ptr(u)) != WEO_OK || (rc = check_ptr(b)) != WEO_OK || (rc = check_ptr(x)) != WEO_OK)
         return rc;
-    if (p->mixed && (rc = check_ptr(u_inner)) != WEO_OK) return rc;
+    const bool pre64 = p->method == WEO_SOLVER_SAP_GCR && !p->mixed && fmt_info(id).spinor_prec == WEO_F64;
+    if ((p->mixed || pre64) && (rc = check_ptr(u_inner)) != WEO_OK) return rc;
+    SapGeom sg;
+    std::memset(&sg, 0, sizeof(sg));
+    if (p->method == WEO_SOLVER_SAP_GCR && make_sap_geom(g, p->sap.block, &sg) != 0) return WEO_ERR_ARG;
     if (p->clover && (rc = check_ptr(p->clover)) != WEO_OK) return rc;
     if (p->mixed && p->clover_inner && (rc = check_ptr(p->clover_inner)) != WEO_OK) return rc;
     if ((rc = check_ptr(workspace)) != WEO_OK) return rc == WEO_ERR_ARG ? WEO_ERR_WORKSPACE : rc;
@@ -797,6 +978,14 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
     phases_of(lat, c.ph);
     c.st = static_cast<hipStream_t>(stream);
     c.applies = 0;
+    c.sap = sg;
+    c.ncy = p->sap.ncy;
+    c.nmr = p->sap.nmr;
+    c.nkv = p->gcr_nkv;
+    // the SAP preconditioner's FP32 format and links: the level's own when
+    // its spinors are FP32, else (plain FP64 solve) the inner ones
+    c.fmt_pre = pre64 ? inner : (p->mixed ? inner : id);
+    c.u_pre = (pre64 || p->mixed) ? u_inner : u;
     const uint32_t nbb = blas_blocks(gb);
     std::vector<int> live(n, 1);
     int status = WEO_OK;
@@ -859,7 +1048,7 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             }
             if (!nlive || k >= p->max_outer || inner_iters >= p->maxiter || breakdown) break;
             // inner right-hand side: r64 scaled to unit RMS, in FP32; x_acc = 0
-            HIPCHK(launch_convert(gb, id, r64, kAccF32, w.s_acc, n, w.sc.sc_in, 0, c.st));
+            HIPCHK(convert_fields(c, id, r64, kAccF32, w.s_acc, n, w.sc.sc_in, 0));
             HIPCHK(launch_zero(w.x_acc, (size_t)n * spinor_field_bytes(gb, kAccF32), c.st));
             // the inner stopping test compares with ||rhs||^2 = target
             std::vector<double> tg(n, target);
@@ -874,7 +1063,7 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             inner_iters += lr.iters;
             breakdown = breakdown || lr.breakdown;
             // x += x_acc * sc_out (only live rhs changed: x_acc = 0 elsewhere)
-            HIPCHK(launch_convert(gb, kAccF32, w.x_acc, id, x, n, w.sc.sc_out, 1, c.st));
+            HIPCHK(convert_fields(c, kAccF32, w.x_acc, id, x, n, w.sc.sc_out, 1));
             // restore ||b||^2 (bb0 outlives the copy: the next look synchronises)
             HIPCHK(hipMemcpyAsync(w.sc.bb, bb0.data(), n * sizeof(double), hipMemcpyHostToDevice, c.st));
             ++k;

@@ -182,6 +182,42 @@ hipError_t launch_block_update(const Geom& g, int fmt, int s, const BlockRef& ou
 hipError_t launch_block_qp(const Geom& g, int fmt, int s, const BlockRef& q, const BlockRef& p, const double* ta,
                            const double* tb, hipStream_t st);
 
+// ---- Schwarz alternating procedure and flexible GCR (sap.hip) -----------------
+// Blocks of extent b[mu] (nb[mu] = L_mu / b[mu], each 1 or even; at most 256
+// sites), coloured by the parity of the block coordinates.
+struct SapGeom {
+    int b[4], nb[4];
+    int bvol, nblocks;
+};
+constexpr int kSapMaxSites = 256;
+constexpr int kGcrMax = 16;       // vectors one GCR dot / update pass takes
+// One sweep over the blocks of one colour (nrhs full fields [even | odd] in
+// fmt, FP64 or FP32): nmr MR steps on each block system starting from the
+// carried residual rho (plus kappa H dprev from the previous sweep's block
+// solutions on the neighbouring blocks, dprev may be null); phi += the block
+// solutions, dout = the block solutions, rho = the block residuals.
+hipError_t launch_sap_sweep(const Geom& g, int fmt, const SapGeom& sg, int colour, int nmr, double kappa,
+                            const double ph[4][2], const void* u, void* rho, void* phi, const void* dprev,
+                            void* dout, int nrhs, hipStream_t s);
+// Block layout for extents block[mu] on lattice g: 0 with sg filled, or -1
+// (an extent not dividing L_mu, L_mu / block[mu] neither 1 nor even, or more
+// than kSapMaxSites sites per block).
+int make_sap_geom(const Geom& g, const int block[4], SapGeom* sg);
+// psi = K eta: ncy SAP cycles (colour 0 then 1) from zero, nmr MR steps per
+// block; nrhs full fields in the FP32 format fmt; rho, d0, d1: nrhs full
+// fields of scratch each.
+hipError_t sap_apply(const Geom& g, int fmt, const SapGeom& sg, int ncy, int nmr, double kappa,
+                     const double ph[4][2], const void* u, const void* eta, void* psi, void* rho, void* d0,
+                     void* d1, int nrhs, hipStream_t s);
+// Partials (gcr_wg of them per value) of <a_l, b>, l < n: value 2 l + {re, im}.
+uint32_t gcr_wg(const Geom& gb, int fmt);
+hipError_t launch_gcr_dots(const Geom& gb, int fmt, int n, const void* const* a, const void* b, double* part,
+                           hipStream_t s);
+// b += sum_l (cre_l + i cim_l) a_l; with part: partials of ||b||^2 (value 0)
+// and, when r is given, of <b, r> (values 1, 2: re, im).
+hipError_t launch_gcr_update(const Geom& gb, int fmt, int n, const void* const* a, const double* cre,
+                             const double* cim, void* b, const void* r, double* part, hipStream_t s);
+
 // ---- pack / unpack --------------------------------------------------------
 hipError_t launch_pack_gauge(const Geom& g, int fmt, const void* canon, int canon_f64,
                              void* packed, hipStream_t s);

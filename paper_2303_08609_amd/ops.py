@@ -203,6 +203,23 @@ class Lattice:
                                          _ptr(out), _ptr(tmp), int(nrhs), _stream()), "wilson_eo_clover_apply")
         return out
 
+    # ---- Schwarz alternating procedure (full fields: even half, odd half) -----
+    def sap(self, u, eta, fmt: Format, block=(4, 4, 4, 4), ncy=4, nmr=4, nrhs=1, out=None):
+        """psi = K eta, ncy SAP cycles with nmr MR steps per block solve, on
+        nrhs full fields (FP32 format)."""
+        sp = W.weo_sap_params()
+        for i in range(4):
+            sp.block[i] = int(block[i])
+        sp.ncy, sp.nmr = int(ncy), int(nmr)
+        nbytes = W.wilson_eo_sap_workspace_bytes(self.c, fmt.c, int(nrhs))
+        if nbytes == 0:
+            raise W.WilsonEOError(W.WEO_ERR_ARG, "wilson_eo_sap_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=eta.device)
+        out = self.new_spinor(fmt, 2 * nrhs) if out is None else out
+        W.check(W.wilson_eo_sap(self.c, fmt.c, sp, _ptr(u), _ptr(eta), _ptr(out), _ptr(ws), nbytes, int(nrhs),
+                                _stream()), "wilson_eo_sap")
+        return out
+
     def apply(self, u, x, fmt: Format, dagger=False, nrhs=1, out=None, tmp=None):
         out = self.new_spinor(fmt, nrhs) if out is None else out
         tmp = self.new_spinor(fmt, nrhs) if tmp is None else tmp

@@ -19,15 +19,19 @@ from .ops import Format, Lattice, _ptr, _stream
 OPS = {"M": W.WEO_OP_M, "MdagM": W.WEO_OP_MDAGM, "DW": W.WEO_OP_DW}
 
 
-METHODS = {"cg": W.WEO_SOLVER_CG, "bicgstab": W.WEO_SOLVER_BICGSTAB, "blockcg": W.WEO_SOLVER_BLOCK_CG}
+METHODS = {"cg": W.WEO_SOLVER_CG, "bicgstab": W.WEO_SOLVER_BICGSTAB, "blockcg": W.WEO_SOLVER_BLOCK_CG,
+           "sapgcr": W.WEO_SOLVER_SAP_GCR}
 
 
 def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000, x0=None,
        inner: Format | None = None, u_inner=None, inner_tol=1e-3, max_outer=100,
-       check_every=10, out=None, method="cg", clover=None, clover_inner=None):
+       check_every=10, out=None, method="cg", clover=None, clover_inner=None,
+       sap_block=(4, 4, 4, 4), sap_ncy=4, sap_nmr=4, gcr_nkv=8, pre: Format | None = None):
     """Returns (x, info dict).  ``inner`` switches on FP64 defect correction;
-    ``method`` "cg" (CGLS / CG), "bicgstab" or "blockcg" (also for the inner
-    solves);
+    ``method`` "cg" (CGLS / CG), "bicgstab", "blockcg" or "sapgcr" (flexible
+    GCR with the SAP preconditioner, op "DW" only; also for the inner
+    solves); ``pre``: the FP32 format of the SAP preconditioner's links
+    (passed as ``u_inner``) when a plain "sapgcr" solve runs in FP64;
     ``clover`` / ``clover_inner``: packed inverse site blocks (clover-type M)."""
     p = W.weo_solver_params()
     p.op = OPS[op]
@@ -44,6 +48,13 @@ def cg(lat: Lattice, fmt: Format, u, b, nrhs=1, op="M", tol=1e-6, maxiter=20000,
     p.method = METHODS[method]
     p.clover = _ptr(clover)
     p.clover_inner = _ptr(clover_inner)
+    for i in range(4):
+        p.sap.block[i] = int(sap_block[i])
+    p.sap.ncy = int(sap_ncy)
+    p.sap.nmr = int(sap_nmr)
+    p.gcr_nkv = int(gcr_nkv)
+    if pre is not None and inner is None:
+        p.inner = pre.c
     nbytes = W.wilson_eo_cg_workspace_bytes(lat.c, fmt.c, p)
     if nbytes == 0:
         raise W.WilsonEOError(W.WEO_ERR_ARG, "wilson_eo_cg_workspace_bytes")

@@ -28,7 +28,7 @@ WEO_LINK18, WEO_LINK12 = 0, 1
 WEO_MAX_RHS = 16
 WEO_NOALLOC_SCRATCH_BYTES = 134217728
 WEO_OP_M, WEO_OP_MDAGM, WEO_OP_DW = 0, 1, 2
-WEO_SOLVER_CG, WEO_SOLVER_BICGSTAB, WEO_SOLVER_BLOCK_CG = 0, 1, 2
+WEO_SOLVER_CG, WEO_SOLVER_BICGSTAB, WEO_SOLVER_BLOCK_CG, WEO_SOLVER_SAP_GCR = 0, 1, 2, 3
 WEO_FORCE_PROJECT, WEO_FORCE_ACCUMULATE = 1, 2
 
 
@@ -40,11 +40,16 @@ class weo_format(C.Structure):
     _fields_ = [("spinor_prec", C.c_int), ("link_prec", C.c_int), ("link_fmt", C.c_int)]
 
 
+class weo_sap_params(C.Structure):
+    _fields_ = [("block", C.c_int * 4), ("ncy", C.c_int), ("nmr", C.c_int)]
+
+
 class weo_solver_params(C.Structure):
     _fields_ = [("op", C.c_int), ("nrhs", C.c_int), ("tol", C.c_double), ("maxiter", C.c_int),
                 ("x0_given", C.c_int), ("mixed", C.c_int), ("inner", weo_format),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
-                ("method", C.c_int), ("clover", C.c_void_p), ("clover_inner", C.c_void_p)]
+                ("method", C.c_int), ("clover", C.c_void_p), ("clover_inner", C.c_void_p),
+                ("sap", weo_sap_params), ("gcr_nkv", C.c_int)]
 
 
 class weo_solver_info(C.Structure):
@@ -94,6 +99,9 @@ _SIGS = {
                                                   _P(weo_solver_params)]),
     "wilson_eo_cg": (C.c_int, [_P(weo_lattice), _P(weo_format), _P(weo_solver_params), _vp, _vp,
                                _vp, _vp, _vp, C.c_size_t, _P(weo_solver_info), _vp]),
+    "wilson_eo_sap_workspace_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format), C.c_int]),
+    "wilson_eo_sap": (C.c_int, [_P(weo_lattice), _P(weo_format), _P(weo_sap_params), _vp, _vp, _vp, _vp,
+                                C.c_size_t, C.c_int, _vp]),
     "wilson_eo_force": (C.c_int, [_P(weo_lattice), _P(weo_format), _vp, _vp, _vp, _vp, _vp,
                                   C.c_double, C.c_int, _vp, C.c_int, _vp]),
 }
@@ -183,6 +191,8 @@ wilson_eo_face_unpack = _call("wilson_eo_face_unpack")
 wilson_eo_cg_workspace_bytes = _call("wilson_eo_cg_workspace_bytes")
 wilson_eo_cg = _call("wilson_eo_cg")
 wilson_eo_force = _call("wilson_eo_force")
+wilson_eo_sap_workspace_bytes = _call("wilson_eo_sap_workspace_bytes")
+wilson_eo_sap = _call("wilson_eo_sap")
 wilson_eo_strerror = _call("wilson_eo_strerror")
 
 

@@ -206,11 +206,67 @@ def test_block_cg_parameters_without_gpu():
     f16 = W.make_format(W.WEO_F16, W.WEO_F16, W.WEO_LINK12)
     assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(W.WEO_SOLVER_BLOCK_CG, mixed=1, inner=f16)) == 0
     assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(W.WEO_SOLVER_CG, mixed=1, inner=f16)) > 0
-    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(3)) == 0
-    # D_W solves run at one precision level
+    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(4)) == 0
+    # D_W solves: one precision level, or defect correction around FP32 inner
+    # solves (FP16 / BF16 inner spinors are refused for D_W)
     for m in (W.WEO_SOLVER_CG, W.WEO_SOLVER_BICGSTAB, W.WEO_SOLVER_BLOCK_CG):
-        assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(m, mixed=1, inner=f32, op=W.WEO_OP_DW)) == 0
+        assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(m, mixed=1, inner=f32, op=W.WEO_OP_DW)) > 0
+        assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(m, mixed=1, inner=f16, op=W.WEO_OP_DW)) == 0
         assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(m, op=W.WEO_OP_DW)) > 0
+
+
+def test_sap_parameters_without_gpu():
+    """SAP and SAP-GCR argument checks before any device work: block extents
+    must divide the lattice into 1 or an even number of blocks per direction
+    with at most 256 sites each; FP32 spinors and links for the
+    preconditioner; D_W only; restart length 1..16."""
+    lat = W.make_lattice((8, 8, 8, 16), 0.126)
+    f32, f64 = W.make_format(W.WEO_F32), W.make_format(W.WEO_F64)
+    f32l12 = W.make_format(W.WEO_F32, W.WEO_F32, W.WEO_LINK12)
+    f16 = W.make_format(W.WEO_F16, W.WEO_F16, W.WEO_LINK12)
+    full = 8 * 8 * 8 * 16 * 96                       # one FP32 full field
+    assert W.wilson_eo_sap_workspace_bytes(lat, f32, 2) == 3 * 2 * full
+    assert W.wilson_eo_sap_workspace_bytes(lat, f64, 1) == 0
+    assert W.wilson_eo_sap_workspace_bytes(lat, f16, 1) == 0
+    a, b, c, d = 1 << 28, 2 << 28, 3 << 28, 4 << 28     # fake aligned, disjoint: rejected first
+
+    def sp(block, ncy=2, nmr=4):
+        q = W.weo_sap_params()
+        for i in range(4):
+            q.block[i] = block[i]
+        q.ncy, q.nmr = ncy, nmr
+        return q
+    ws = 3 * full
+    assert W.wilson_eo_sap(lat, f32, sp((3, 4, 4, 4)), a, b, c, d, ws, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_sap(lat, f32, sp((8, 8, 8, 16)), a, b, c, d, ws, 1, None) == W.WEO_ERR_ARG  # 8192 sites
+    assert W.wilson_eo_sap(lat, f32, sp((4, 4, 4, 8)), a, b, c, d, ws, 1, None) == W.WEO_ERR_ARG   # 512 sites
+    lat6 = W.make_lattice((12, 8, 8, 16), 0.126)
+    assert W.wilson_eo_sap(lat6, f32, sp((4, 4, 4, 4)), a, b, c, d, 1 << 30, 1, None) == W.WEO_ERR_ARG  # 3 blocks
+    assert W.wilson_eo_sap(lat, f32, sp((4, 4, 4, 4), ncy=0), a, b, c, d, ws, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_sap(lat, f32, sp((4, 4, 4, 4), nmr=65), a, b, c, d, ws, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_sap(lat, f64, sp((4, 4, 4, 4)), a, b, c, d, ws, 1, None) == W.WEO_ERR_FORMAT
+    assert W.wilson_eo_sap(lat, f32, sp((4, 4, 4, 4)), a, b, c, d, ws - 256, 1, None) == W.WEO_ERR_WORKSPACE
+    assert W.wilson_eo_sap(lat, f32, sp((4, 4, 4, 4)), a, b, b, d, ws, 1, None) == W.WEO_ERR_ARG      # psi = eta
+
+    def params(mixed=0, inner=None, op=W.WEO_OP_DW, nkv=8, block=(4, 4, 4, 4)):
+        p = W.weo_solver_params()
+        p.op, p.nrhs, p.tol, p.maxiter, p.check_every = op, 2, 1e-10, 100, 10
+        p.mixed, p.inner_tol, p.max_outer, p.method = mixed, 1e-3, 10, W.WEO_SOLVER_SAP_GCR
+        p.sap = sp(block)
+        p.gcr_nkv = nkv
+        if inner is not None:
+            p.inner = inner
+        return p
+    assert W.wilson_eo_cg_workspace_bytes(lat, f32, params()) > 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f32l12, params()) > 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(inner=f32)) > 0          # FP32 preconditioner
+    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(inner=f64)) == 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(mixed=1, inner=f32l12)) > 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f64, params(mixed=1, inner=f16)) == 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f32, params(op=W.WEO_OP_M)) == 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f32, params(nkv=0)) == 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f32, params(nkv=17)) == 0
+    assert W.wilson_eo_cg_workspace_bytes(lat, f32, params(block=(3, 4, 4, 4))) == 0
 
 
 def test_noalloc_apply_rejects_oversize_before_device_work():

@@ -272,11 +272,12 @@ def test_twelve_source_solve_32_3x64_sampled(inner, method):
         assert np.linalg.norm(x[r][sites]) > 0.1 * np.linalg.norm(br)
 
 
-def test_block_cg_mixed_mdagm_and_dw_rejected():
+def test_block_cg_mixed_mdagm_and_dw_fp16_rejected():
     """FP64 defect correction around FP32 block inner solves for M^dag M X = B
     (4 sources) to 1e-10 against the oracle's residuals; on D_W (full fields)
-    defect correction is refused with an argument error."""
-    print("block cg mixed MdagM; D_W mixed rejected", flush=True)
+    defect correction with FP16 inner spinors is refused (the FP32 case is
+    tested with the other D_W solves)."""
+    print("block cg mixed MdagM; D_W mixed FP16 rejected", flush=True)
     from tests.test_gpu_solver import _full_field
     dims, kappa = (6, 4, 4, 8), 0.125
     lat = Lattice(dims, kappa, AP)
@@ -292,6 +293,8 @@ def test_block_cg_mixed_mdagm_and_dw_rejected():
     for j in range(4):
         assert S.rel_resid(lambda v: md(m(v)), x[j], b[j]) <= 1e-10, j
     bf = _full_field(lat, F64, inputs.gen_spinor_full(dims, 222))
+    f16 = Format("f16", "f16", 12)
+    u16 = lat.pack_gauge(ud, f16)
     for meth in ("cg", "blockcg"):
         with pytest.raises(WE.WilsonEOError):
-            cg(lat, F64, u64, bf, op="DW", tol=1e-10, inner=F32, u_inner=u32, maxiter=10, method=meth)
+            cg(lat, F64, u64, bf, op="DW", tol=1e-10, inner=f16, u_inner=u16, maxiter=10, method=meth)
