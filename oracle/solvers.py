@@ -126,10 +126,31 @@ def bicgstab(apply_a, b, tol, maxiter, x0=None):
     return x, it, hist
 
 
-def _block_qr(z):
-    """Thin Householder QR of the n x s block z (columns are the rhs)."""
-    q, r = np.linalg.qr(z, mode="reduced")
-    return q, r
+RANK_EPS = 64 * 2.0 ** -53
+
+
+def _block_qr(z, rank_eps=RANK_EPS):
+    """Thin QR of the n x s block z with deflation: z = Q psi, Q (n x r)
+    orthonormal over the columns that are independent, psi (r x s) the
+    coefficients of every column of z in that basis.  The columns are taken
+    in order; column j is dropped when the part of it orthogonal to the
+    columns kept before it has squared norm <= rank_eps ||z_j||^2 (it is
+    then, to that accuracy, a combination of them).  Q is the Householder QR
+    of the kept columns."""
+    kept = []
+    for j in range(z.shape[1]):
+        nj = np.linalg.norm(z[:, j]) ** 2
+        if kept:
+            qk, _ = np.linalg.qr(z[:, kept], mode="reduced")
+            perp = z[:, j] - qk @ (qk.conj().T @ z[:, j])
+        else:
+            perp = z[:, j]
+        if np.linalg.norm(perp) ** 2 > rank_eps * nj:
+            kept.append(j)
+    if not kept:
+        return np.zeros((z.shape[0], 0), dtype=z.dtype), np.zeros((0, z.shape[1]), dtype=z.dtype)
+    q, _ = np.linalg.qr(z[:, kept], mode="reduced")
+    return q, q.conj().T @ z
 
 
 def block_cg(apply_a, b, tol, maxiter, apply_m=None, apply_mdag=None):
@@ -141,7 +162,10 @@ def block_cg(apply_a, b, tol, maxiter, apply_m=None, apply_mdag=None):
     carries S = B - M X.
 
     The residual block of the system solved is kept as R = Q C with Q
-    orthonormal (n x s) and C (s x s); the search block P satisfies P^H Q = I:
+    orthonormal (n x r) and C (r x s), r <= s the rank of the block (columns
+    that become dependent are deflated by ``_block_qr``: the block shrinks
+    and the dropped directions' coefficients stay in C); the search block P
+    (n x r) satisfies P^H Q = I:
         start   Q C = R_0 (QR),  P = Q
         repeat  W = A P,  delta = (P^H W)^-1
                 X += P delta C       (S -= (M P) delta C)
@@ -173,7 +197,7 @@ def block_cg(apply_a, b, tol, maxiter, apply_m=None, apply_mdag=None):
 
     hist = [rel()]
     it = 0
-    while hist[-1] > tol and it < maxiter:
+    while hist[-1] > tol and it < maxiter and q.shape[1] > 0:
         if normal:
             mp = blk(apply_m, p)
             w = blk(apply_mdag, mp)

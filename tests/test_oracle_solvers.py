@@ -188,3 +188,31 @@ def test_block_cg_normal_equations_on_the_wilson_operator():
         assert S.rel_resid(m, x[j], b[j]) <= 1e-11
         want = np.linalg.solve(d, b[j].reshape(-1)).reshape(b[j].shape)
         assert np.linalg.norm(x[j] - want) / np.linalg.norm(want) < 1e-9
+
+
+def test_block_cg_deflates_dependent_columns():
+    """Columns of B that are combinations of others are deflated, not a
+    breakdown: the iterate of each column equals block CG run on the
+    independent columns alone (the same block Krylov space), a duplicated
+    column equals its twin and a combination equals the same combination of
+    the solutions, at every iteration; converged, each column is the dense
+    solution."""
+    n = 40
+    a = _hpd(n, 11)
+    rng = np.random.default_rng(12)
+    b0, b1 = (rng.standard_normal(n) + 1j * rng.standard_normal(n) for _ in range(2))
+    apply_a = lambda v: a @ v
+    for k in (1, 2, 4):
+        x, it, _ = S.block_cg(apply_a, [b0, b1, b0, b0 + 2.0 * b1], 1e-30, k)
+        xi, _, _ = S.block_cg(apply_a, [b0, b1], 1e-30, k)
+        assert it == k
+        assert np.linalg.norm(x[0] - xi[0]) / np.linalg.norm(xi[0]) < 1e-11, k
+        assert np.linalg.norm(x[1] - xi[1]) / np.linalg.norm(xi[1]) < 1e-11, k
+        assert np.linalg.norm(x[2] - x[0]) / np.linalg.norm(x[0]) < 1e-11, k
+        assert np.linalg.norm(x[3] - (x[0] + 2.0 * x[1])) / np.linalg.norm(x[3]) < 1e-11, k
+    x, it, hist = S.block_cg(apply_a, [b0, b0, b1], 1e-11, 100)
+    assert hist[-1] <= 1e-11
+    for xj, bj in zip(x, [b0, b0, b1]):
+        assert np.linalg.norm(xj - np.linalg.solve(a, bj)) / np.linalg.norm(xj) < 1e-9
+    q, psi = S._block_qr(np.stack([b0, b1, b0, 3.0 * b1], axis=1))
+    assert q.shape == (n, 2) and psi.shape == (2, 4)
