@@ -307,8 +307,10 @@ int wilson_eo_apply_noalloc(const weo_lattice* lat, const weo_format* fmt, int d
                                     normal equations (carrying b - M x) for
                                     WEO_OP_M / WEO_OP_DW.  FP64 or FP32 vectors
                                     only (a mixed solve needs FP32 inner spinors);
-                                    WEO_BREAKDOWN when the block loses rank (e.g.
-                                    two equal rhs) */
+                                    residual columns that become dependent (e.g.
+                                    two equal rhs) are deflated: the block
+                                    shrinks and the dropped columns follow the
+                                    others' coefficients */
 #define WEO_SOLVER_SAP_GCR   3   /* flexible GCR (restart gcr_nkv) preconditioned by
                                     the Schwarz alternating procedure (params sap),
                                     WEO_OP_DW only; the right-hand sides are solved
@@ -396,8 +398,7 @@ size_t wilson_eo_cg_workspace_bytes(const weo_lattice* lat, const weo_format* fm
  * With WEO_SOLVER_BLOCK_CG the right-hand sides whose start does not already
  * meet the tolerance form one block (the others are left as they are);
  * info->iters counts block iterations; the block method needs FP64 or FP32
- * spinors (else WEO_ERR_FORMAT) and ends with WEO_BREAKDOWN if the block
- * loses rank. */
+ * spinors (else WEO_ERR_FORMAT); dependent residual columns are deflated. */
 int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt,
                  const weo_solver_params* p,
                  const void* u, const void* u_inner,

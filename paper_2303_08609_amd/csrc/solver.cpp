@@ -564,14 +564,74 @@ void to_dev_layout(const Mat& m, double* out) {
             out[(i * m.n + j) * 2 + 1] = m(i, j).imag();
         }
 }
+// Cholesky factorisation of a Gram matrix G = Z^H Z (n x n) that deflates
+// dependent columns: the columns are taken in order, and column i is kept
+// when the part of z_i orthogonal to the kept columns before it has squared
+// norm d > rank_eps G_ii (the squared sine of its angle to their span), else
+// dropped.  On return kept lists the r kept columns and l (n x n, only the
+// first r columns used) satisfies G_ij = sum_k l(i, k) conj(l(j, k)) for every
+// i, j to that accuracy: with Q = Z_kept L_kk^-H (L_kk the kept rows of l),
+// z_j = sum_k Q_k conj(l(j, k)).  False on a non-finite entry.
+bool cholesky_deflate(const Mat& gm, Mat& l, std::vector<int>& kept, double rank_eps) {
+    const int n = gm.n;
+    l = Mat(n);
+    kept.clear();
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < (int)kept.size(); ++k) {
+            const int jk = kept[k];
+            cplx v = gm(i, jk);
+            for (int q = 0; q < k; ++q) v -= l(i, q) * std::conj(l(jk, q));
+            l(i, k) = v / l(jk, k).real();
+        }
+        double d = gm(i, i).real();
+        for (int k = 0; k < (int)kept.size(); ++k) d -= std::norm(l(i, k));
+        if (!std::isfinite(d)) return false;
+        if (d > rank_eps * gm(i, i).real()) {
+            l(i, (int)kept.size()) = std::sqrt(d);
+            kept.push_back(i);
+        }
+    }
+    return true;
+}
+// The factors of a deflating QR Z = Q psi (Z with n columns, r kept): T with
+// Q = Z T (n x r: row kept[k] holds column k of L_kk^-H, other rows zero)
+// and psi^H = l restricted to its first r columns (n x r); both padded to
+// n x n with zero columns from r on.
+void deflate_factors(const Mat& l, const std::vector<int>& kept, Mat& t, Mat& psih) {
+    const int n = l.n, r = (int)kept.size();
+    Mat lkk(r);
+    for (int a = 0; a < r; ++a)
+        for (int b = 0; b < r; ++b) lkk(a, b) = l(kept[a], b);
+    const Mat li = lower_inv(lkk);
+    t = Mat(n);
+    psih = Mat(n);
+    for (int a = 0; a < r; ++a)
+        for (int m = 0; m < r; ++m) t(kept[a], m) = std::conj(li(m, a));
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < r; ++k) psih(i, k) = l(i, k);
+}
+// The leading r x r block of an n x n matrix, and back (zero padded).
+Mat lead(const Mat& m, int r) {
+    Mat z(r);
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) z(i, j) = m(i, j);
+    return z;
+}
+Mat pad(const Mat& m, int n) {
+    Mat z(n);
+    for (int i = 0; i < m.n && i < n; ++i)
+        for (int j = 0; j < m.n && j < n; ++j) z(i, j) = m(i, j);
+    return z;
+}
 
 // Block CG at one precision level (vectors in one FP64 or FP32 format).  Same
 // contract as run_level: x_acc holds the start, s_acc the residual b - M x
 // (b - A x for M^dag M), mask the live rhs, bb[r] = ||b||^2.  The live rhs
 // form one block; it stops when every one of them meets ||r||^2 <= tol^2 bb
 // (r = S, or the recurrence ||C e_j||^2 for M^dag M).  Block vectors: Q = r,
-// P = p, W = q, M P = t (fields 0 .. s-1).  Breakdown: a Gram matrix that is
-// not numerically positive definite (rank loss of the block).
+// P = p, W = q, M P = t (fields 0 .. s-1).  Columns of the residual block
+// that become dependent are deflated (the block shrinks); breakdown: P^H A P
+// not numerically positive definite, or a non-finite Gram matrix.
 int run_level_block(Ctx& c, const Workspace& w, int op, int fmt, const void* u, void* x_acc, int nrhs,
                     double tol, int maxiter, LevelResult* res) {
     const Geom& g = c.gb;
@@ -623,23 +683,32 @@ int run_level_block(Ctx& c, const Workspace& w, int op, int fmt, const void* u, 
     double* d_dl = w.tm + 2 * kGramStride;
     double* d_pi = w.tm + 3 * kGramStride;
     double* d_ph = w.tm + 4 * kGramStride;
+    // a factor laid out for kernels of width m.n
     auto upload = [&](const Mat& m, std::vector<double>& h, double* d) -> hipError_t {
         to_dev_layout(m, h.data());
-        return hipMemcpyAsync(d, h.data(), (size_t)2 * s * s * sizeof(double), hipMemcpyHostToDevice, c.st);
+        return hipMemcpyAsync(d, h.data(), (size_t)2 * m.n * m.n * sizeof(double), hipMemcpyHostToDevice, c.st);
     };
-    auto gram = [&](const BlockRef& a, const BlockRef& b, Mat& out) -> hipError_t {
-        hipError_t e = launch_block_gram(g, fmt, s, a, b, w.gpart, w.gram, c.st);
+    // Gram matrix of the first n columns of two blocks (and ||S_j||^2)
+    auto gram = [&](const BlockRef& a, const BlockRef& b, Mat& out, int n) -> hipError_t {
+        hipError_t e = launch_block_gram(g, fmt, n, a, b, w.gpart, w.gram, c.st);
         if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(gh.data(), w.gram, (size_t)2 * s * s * sizeof(double), hipMemcpyDeviceToHost, c.st);
+        e = hipMemcpyAsync(gh.data(), w.gram, (size_t)2 * n * n * sizeof(double), hipMemcpyDeviceToHost, c.st);
         if (e != hipSuccess) return e;
         if (normal) {
             e = hipMemcpyAsync(ssv.data(), w.sc.ss, s * sizeof(double), hipMemcpyDeviceToHost, c.st);
             if (e != hipSuccess) return e;
         }
         e = hipStreamSynchronize(c.st);
-        out = gram_from(gh, s);
+        out = gram_from(gh, n);
         return e;
     };
+    // Deflation: the block (Q, P, W, M P) has r <= s columns, the first r of
+    // its fields; columns of the residual block that become dependent are
+    // dropped by cholesky_deflate, the block shrinks and C (r x s, held as an
+    // s x s matrix with zero rows from r on) keeps their coefficients.  X and
+    // S keep all s columns: their updates run at width s with zero rows of
+    // the coefficient matrix for the dropped directions (the block fields
+    // beyond r hold finite values from earlier steps).
     HIPCHK(upload(Mat::eye(s), h_id, d_id));
     // R_0 = S (M^dag M) or A^dag S, gathered into W; ||S_j||^2 into ss
     if (normal) {
@@ -648,11 +717,15 @@ int run_level_block(Ctx& c, const Workspace& w, int op, int fmt, const void* u, 
     } else {
         HIPCHK(launch_block_update(g, fmt, s, W, nullptr, S, 1.0, d_id, nullptr, nullptr, c.st));
     }
-    Mat gm(s), l(s);
-    HIPCHK(gram(W, W, gm));
-    if (!cholesky(gm, l, rank_eps)) { res->breakdown = 1; return WEO_OK; }
-    Mat cm = adj(l);                                   // C = psi_0 (R_0 = Q C)
-    HIPCHK(upload(adj(lower_inv(l)), h_pi, d_pi));     // Q = R_0 psi_0^-1
+    Mat gm(s), l(s), t(s), psih(s);
+    std::vector<int> kept;
+    HIPCHK(gram(W, W, gm, s));
+    if (!cholesky_deflate(gm, l, kept, rank_eps)) { res->breakdown = 1; return WEO_OK; }
+    int r = (int)kept.size();
+    if (!r) return WEO_OK;
+    deflate_factors(l, kept, t, psih);
+    Mat cm = adj(psih);                                // C = psi_0 (R_0 = Q C)
+    HIPCHK(upload(t, h_pi, d_pi));                     // Q = R_0 T
     HIPCHK(launch_block_update(g, fmt, s, Q, nullptr, W, 1.0, d_pi, nullptr, nullptr, c.st));
     HIPCHK(launch_block_update(g, fmt, s, P, nullptr, Q, 1.0, d_id, nullptr, nullptr, c.st));
     auto converged = [&]() {
@@ -669,29 +742,37 @@ int run_level_block(Ctx& c, const Workspace& w, int op, int fmt, const void* u, 
     for (int it = 1; it <= maxiter; ++it) {
         // W = A P (M P kept for S)
         if (normal) {
-            HIPCHK(apply_a(c, fmt, u, 0, w.p, w.t, w.tmp, s, nullptr));
-            HIPCHK(apply_a(c, fmt, u, 1, w.t, w.q, w.tmp, s, nullptr));
+            HIPCHK(apply_a(c, fmt, u, 0, w.p, w.t, w.tmp, r, nullptr));
+            HIPCHK(apply_a(c, fmt, u, 1, w.t, w.q, w.tmp, r, nullptr));
         } else {
-            HIPCHK(apply_op(c, op, fmt, u, w.p, w.q, w.t, w.tmp, s, nullptr));
+            HIPCHK(apply_op(c, op, fmt, u, w.p, w.q, w.t, w.tmp, r, nullptr));
         }
-        HIPCHK(gram(P, W, gm));
-        if (!cholesky(gm, l, rank_eps)) { res->breakdown = 1; break; }
-        const Mat li = lower_inv(l);
+        Mat gpw(r), lpw(r);
+        HIPCHK(gram(P, W, gpw, r));
+        if (!cholesky(gpw, lpw, rank_eps)) { res->breakdown = 1; break; }
+        const Mat li = lower_inv(lpw);
         const Mat delta = mul(adj(li), li);            // (P^H W)^-1
-        HIPCHK(upload(mul(delta, cm), h_dc, d_dc));
+        HIPCHK(upload(mul(pad(delta, s), cm), h_dc, d_dc));
         HIPCHK(upload(delta, h_dl, d_dl));
         HIPCHK(launch_block_update(g, fmt, s, X, &X, P, 1.0, d_dc, nullptr, nullptr, c.st));
         if (normal) HIPCHK(launch_block_update(g, fmt, s, S, &S, MP, -1.0, d_dc, w.upart, w.sc.ss, c.st));
-        HIPCHK(launch_block_update(g, fmt, s, Q, &Q, W, -1.0, d_dl, nullptr, nullptr, c.st));
-        HIPCHK(gram(Q, Q, gm));
+        HIPCHK(launch_block_update(g, fmt, r, Q, &Q, W, -1.0, d_dl, nullptr, nullptr, c.st));
+        Mat gq(r);
+        HIPCHK(gram(Q, Q, gq, r));
         res->iters = it;
-        if (!cholesky(gm, l, rank_eps)) { res->breakdown = 1; break; }
-        const Mat psi = adj(l);
-        cm = mul(psi, cm);
-        if (converged()) break;
-        HIPCHK(upload(adj(lower_inv(l)), h_pi, d_pi));  // psi^-1 = (L^-1)^H
-        HIPCHK(upload(l, h_ph, d_ph));                   // psi^H = L
-        HIPCHK(launch_block_qp(g, fmt, s, Q, P, d_pi, d_ph, c.st));
+        // the carried residuals of the normal equations decide before the
+        // new residual block is factorised
+        if (normal && converged()) break;
+        Mat lq(r), tq(r), pq(r);
+        if (!cholesky_deflate(gq, lq, kept, rank_eps)) { res->breakdown = 1; break; }
+        const int r2 = (int)kept.size();
+        deflate_factors(lq, kept, tq, pq);
+        cm = mul(pad(adj(pq), s), cm);                 // C = psi C
+        if (converged() || !r2) break;
+        HIPCHK(upload(tq, h_pi, d_pi));                // Q' = Q T
+        HIPCHK(upload(pq, h_ph, d_ph));                // psi^H
+        HIPCHK(launch_block_qp(g, fmt, r, Q, P, d_pi, d_ph, c.st));
+        r = r2;
     }
     HIPCHK(hipStreamSynchronize(c.st));
     return WEO_OK;
