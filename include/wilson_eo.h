@@ -174,44 +174,51 @@ int wilson_eo_hop_axpy(const weo_lattice* lat, const weo_format* fmt,
                        const void* u, const void* in, const void* y, void* out,
                        int nrhs, void* stream);
 
-/* ---- a hop split along t (domain decomposition, Sec. 3.6 and 4.1) --------
- * A device holding a slab of consecutive t slices (even length) computes its
- * share of a hop in three calls:
- *   1. wilson_eo_hop / wilson_eo_hop_axpy on the slab with bc[t] = {0, 0}:
- *      a zero phase drops exactly the terms that cross the slab's t faces;
- *   2. wilson_eo_face_pack: the two faces its neighbours need, from the
- *      input field (parity 1 - out_parity);
- *   3. after the exchange, wilson_eo_face_unpack adds the two received
- *      faces to the output (slices t = 0 and t = Lt-1).
- * Face f of a slice is the site (x, y, z) of one parity with
- * f = (x >> 1) + Lx/2 (y + Ly z); it holds the two non-zero spin rows of the
- * t-projected spinor (6 complex in the spinor precision):
- *   send_lo[f] = (1 - S gamma_t) in(f, t = 0)                 -> slab below
- *   send_hi[f] = U_t(f, Lt-1)^dag (1 + S gamma_t) in(f, Lt-1)  -> slab above
+/* ---- a hop split along a direction (domain decomposition, Sec. 3.6, 4.1) ---
+ * A device holding a block of consecutive mu slices (even length) of the
+ * lattice computes its share of a hop in three calls per split direction mu:
+ *   1. wilson_eo_hop / wilson_eo_hop_axpy on the block with bc[mu] = {0, 0}
+ *      for every split direction: a zero phase drops exactly the terms that
+ *      cross the block's mu faces;
+ *   2. wilson_eo_face_pack: the two faces its neighbours along mu need, from
+ *      the input field (parity 1 - out_parity);
+ *   3. after the exchange, wilson_eo_face_unpack adds the two received faces
+ *      to the output (slices x_mu = 0 and x_mu = L_mu - 1).
+ * Each face holds, per site of one parity, the two-component half spinor of
+ * the projected input (6 complex in the spinor precision):
+ *   send_lo[f] = (1 - S gamma_mu) psi(f, x_mu = 0)                   -> block below
+ *   send_hi[f] = U_mu(f, L_mu-1)^dag (1 + S gamma_mu) psi(f, x_mu = L_mu-1) -> block above
  * with S = +1 (dagger 0) or -1 (dagger 1): the backward face is multiplied
- * by the link on the sender, which owns it.  The receiver's recv_lo is the
- * slab below's send_hi and recv_hi the slab above's send_lo; on one device
- * holding the whole lattice recv_lo = send_hi and recv_hi = send_lo (the
- * paper's exchange with itself).  Face buffers hold nrhs faces of
- * weo_face_bytes(lat, fmt, 1) bytes each; layout private to the library. */
-size_t weo_face_bytes(const weo_lattice* lat, const weo_format* fmt, int nrhs);
+ * by the link on the sender, which owns it.  The receiver rebuilds the full
+ * spinor from the half spinor.  Face sites f: for y, z, t the sites of the
+ * slice in the library's compacted order (x/2 fastest, then the remaining
+ * coordinates in x, y, z, t order); for x, where the slice holds one parity
+ * only in every other (y, z, t) row, f = (y + Ly (z + Lz t)) / 2.  With an
+ * even block length the sites across a face carry the same f on both sides.
+ * The receiver's recv_lo is the block below's send_hi and recv_hi the block
+ * above's send_lo; on one device holding the whole lattice recv_lo = send_hi
+ * and recv_hi = send_lo (the paper's forced exchange with itself, which its
+ * Table 1 runs use in all four directions).  Face buffers hold nrhs faces of
+ * weo_face_bytes(lat, fmt, mu, 1) bytes each; layout private to the library.
+ * mu outside 0..3: WEO_ERR_ARG (weo_face_bytes: 0). */
+size_t weo_face_bytes(const weo_lattice* lat, const weo_format* fmt, int mu, int nrhs);
 
-/* Pack the two t faces of nrhs input spinors (parity 1 - out_parity) for a
+/* Pack the two mu faces of nrhs input spinors (parity 1 - out_parity) for a
  * hop to out_parity.  send_lo and send_hi must not overlap each other, u or in. */
-int wilson_eo_face_pack(const weo_lattice* lat, const weo_format* fmt,
+int wilson_eo_face_pack(const weo_lattice* lat, const weo_format* fmt, int mu,
                         int out_parity, int dagger,
                         const void* u, const void* in,
                         void* send_lo, void* send_hi, int nrhs, void* stream);
 
-/* Add the received faces to nrhs output spinors of parity out_parity:
- *   out(f, 0)    += alpha * 2 conj(phase_lo) recv_lo[f]   (rows kept by 1 + S gamma_t)
- *   out(f, Lt-1) += alpha * 2 phase_hi U_t(f, Lt-1) recv_hi[f]   (rows of 1 - S gamma_t)
- * phase_lo / phase_hi (host arrays {re, im}) are the t boundary phase for a
- * face that is the global t boundary and {1, 0} otherwise; alpha matches the
+/* Add the received mu faces to nrhs output spinors of parity out_parity:
+ *   out(f, x_mu = 0)      += alpha conj(phase_lo) [(1 + S gamma_mu) part rebuilt from recv_lo[f]]
+ *   out(f, x_mu = L_mu-1) += alpha phase_hi [(1 - S gamma_mu) part rebuilt from U_mu recv_hi[f]]
+ * phase_lo / phase_hi (host arrays {re, im}) are the mu boundary phase for a
+ * face that is the global lattice edge and {1, 0} otherwise; alpha matches the
  * bulk call (1 for wilson_eo_hop, its alpha for wilson_eo_hop_axpy).
  * Must follow the bulk call on the same stream; only the two face slices of
  * out are touched.  recv_lo / recv_hi must not overlap out. */
-int wilson_eo_face_unpack(const weo_lattice* lat, const weo_format* fmt,
+int wilson_eo_face_unpack(const weo_lattice* lat, const weo_format* fmt, int mu,
                           int out_parity, int dagger,
                           const double phase_lo[2], const double phase_hi[2], double alpha,
                           const void* u, const void* recv_lo, const void* recv_hi,

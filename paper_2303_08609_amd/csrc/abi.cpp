@@ -215,15 +215,15 @@ int wilson_eo_hop(const weo_lattice* lat, const weo_format* fmt, int out_parity,
     return hip_status(launch_hop(h, static_cast<hipStream_t>(stream)));
 }
 
-size_t weo_face_bytes(const weo_lattice* lat, const weo_format* fmt, int nrhs) {
+size_t weo_face_bytes(const weo_lattice* lat, const weo_format* fmt, int mu, int nrhs) {
     Geom g;
     int id;
     if (check_lattice(lat, &g) != WEO_OK || check_fmt(fmt, &id) != WEO_OK) return 0;
-    if (nrhs < 1 || nrhs > WEO_MAX_RHS) return 0;
-    return (size_t)nrhs * face_field_bytes(g, id);
+    if (nrhs < 1 || nrhs > WEO_MAX_RHS || mu < 0 || mu > 3) return 0;
+    return (size_t)nrhs * face_field_bytes(g, id, mu);
 }
 
-int wilson_eo_face_pack(const weo_lattice* lat, const weo_format* fmt, int out_parity, int dagger,
+int wilson_eo_face_pack(const weo_lattice* lat, const weo_format* fmt, int mu, int out_parity, int dagger,
                         const void* u, const void* in, void* send_lo, void* send_hi, int nrhs,
                         void* stream) {
     Geom g;
@@ -231,22 +231,23 @@ int wilson_eo_face_pack(const weo_lattice* lat, const weo_format* fmt, int out_p
     WEO_TRY(check_lattice(lat, &g));
     WEO_TRY(check_fmt(fmt, &id));
     if ((out_parity != 0 && out_parity != 1) || (dagger != 0 && dagger != 1)) return WEO_ERR_ARG;
+    if (mu < 0 || mu > 3) return WEO_ERR_ARG;
     if (nrhs < 1 || nrhs > WEO_MAX_RHS) return WEO_ERR_ARG;
     WEO_TRY(check_ptr(u));
     WEO_TRY(check_ptr(in));
     WEO_TRY(check_ptr(send_lo));
     WEO_TRY(check_ptr(send_hi));
     const size_t sb = (size_t)nrhs * spinor_field_bytes(g, id);
-    const size_t fb = (size_t)nrhs * face_field_bytes(g, id);
+    const size_t fb = (size_t)nrhs * face_field_bytes(g, id, mu);
     const size_t ub = gauge_field_bytes(g, id);
     if (overlaps(send_lo, fb, send_hi, fb) || overlaps(send_lo, fb, in, sb) ||
         overlaps(send_hi, fb, in, sb) || overlaps(send_lo, fb, u, ub) || overlaps(send_hi, fb, u, ub))
         return WEO_ERR_ARG;
-    return hip_status(launch_face_pack(g, id, out_parity, dagger, u, in, send_lo, send_hi, nrhs,
+    return hip_status(launch_face_pack(g, id, mu, out_parity, dagger, u, in, send_lo, send_hi, nrhs,
                                        static_cast<hipStream_t>(stream)));
 }
 
-int wilson_eo_face_unpack(const weo_lattice* lat, const weo_format* fmt, int out_parity, int dagger,
+int wilson_eo_face_unpack(const weo_lattice* lat, const weo_format* fmt, int mu, int out_parity, int dagger,
                           const double phase_lo[2], const double phase_hi[2], double alpha,
                           const void* u, const void* recv_lo, const void* recv_hi, void* out,
                           int nrhs, void* stream) {
@@ -255,6 +256,7 @@ int wilson_eo_face_unpack(const weo_lattice* lat, const weo_format* fmt, int out
     WEO_TRY(check_lattice(lat, &g));
     WEO_TRY(check_fmt(fmt, &id));
     if ((out_parity != 0 && out_parity != 1) || (dagger != 0 && dagger != 1)) return WEO_ERR_ARG;
+    if (mu < 0 || mu > 3) return WEO_ERR_ARG;
     if (nrhs < 1 || nrhs > WEO_MAX_RHS || !std::isfinite(alpha)) return WEO_ERR_ARG;
     if (!phase_lo || !phase_hi) return WEO_ERR_ARG;
     for (int k = 0; k < 2; ++k)
@@ -264,11 +266,11 @@ int wilson_eo_face_unpack(const weo_lattice* lat, const weo_format* fmt, int out
     WEO_TRY(check_ptr(recv_hi));
     WEO_TRY(check_ptr(out));
     const size_t sb = (size_t)nrhs * spinor_field_bytes(g, id);
-    const size_t fb = (size_t)nrhs * face_field_bytes(g, id);
+    const size_t fb = (size_t)nrhs * face_field_bytes(g, id, mu);
     if (overlaps(recv_lo, fb, out, sb) || overlaps(recv_hi, fb, out, sb) ||
         overlaps(u, gauge_field_bytes(g, id), out, sb))
         return WEO_ERR_ARG;
-    return hip_status(launch_face_unpack(g, id, out_parity, dagger, phase_lo, phase_hi, alpha, u,
+    return hip_status(launch_face_unpack(g, id, mu, out_parity, dagger, phase_lo, phase_hi, alpha, u,
                                          recv_lo, recv_hi, out, nrhs, static_cast<hipStream_t>(stream)));
 }
 

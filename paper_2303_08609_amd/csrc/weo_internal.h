@@ -226,11 +226,12 @@ hipError_t launch_pack_spinor(const Geom& g, int fmt, int nrhs, const void* cano
 hipError_t launch_unpack_spinor(const Geom& g, int fmt, int nrhs, const void* packed,
                                 double scale, void* canon, int canon_f64, hipStream_t s);
 
-// ---- t-face exchange of a slab hop --------------------------------------------
-size_t face_field_bytes(const Geom& g, int fmt);   // one face of one field
-hipError_t launch_face_pack(const Geom& g, int fmt, int out_par, int dagger, const void* u,
+// ---- face exchange of a hop split along a direction ------------------------------
+uint32_t face_sites(const Geom& g, int mu);                 // face sites per parity
+size_t face_field_bytes(const Geom& g, int fmt, int mu);   // one face of one field
+hipError_t launch_face_pack(const Geom& g, int fmt, int mu, int out_par, int dagger, const void* u,
                             const void* in, void* lo, void* hi, int nrhs, hipStream_t s);
-hipError_t launch_face_unpack(const Geom& g, int fmt, int out_par, int dagger, const double ph_lo[2],
+hipError_t launch_face_unpack(const Geom& g, int fmt, int mu, int out_par, int dagger, const double ph_lo[2],
                               const double ph_hi[2], double alpha, const void* u, const void* lo,
                               const void* hi, void* out, int nrhs, hipStream_t s);
 

@@ -132,32 +132,38 @@ class Lattice:
                 "wilson_eo_hop_axpy")
         return out
 
-    # ---- t-split hop: faces of a slab --------------------------------------
+    # ---- split hop: faces of a block along a direction ------------------------
     def open_t(self):
         """The same slab with a zero t phase: its hop is the bulk part of a
         t-split hop (the terms across the t faces dropped)."""
-        return Lattice(self.dims, self.kappa, self.bc[:3] + (0.0,))
+        return self.open_dirs((3,))
 
-    def face_bytes(self, fmt: Format, nrhs=1) -> int:
-        n = W.weo_face_bytes(self.c, fmt.c, int(nrhs))
+    def open_dirs(self, dirs):
+        """The same block with zero phases in the split directions ``dirs``:
+        its hop is the bulk part of the split hop."""
+        return Lattice(self.dims, self.kappa, tuple(0.0 if m in dirs else b for m, b in enumerate(self.bc)))
+
+    def face_bytes(self, fmt: Format, nrhs=1, mu=3) -> int:
+        n = W.weo_face_bytes(self.c, fmt.c, int(mu), int(nrhs))
         if n == 0:
             raise W.WilsonEOError(W.WEO_ERR_ARG, "weo_face_bytes")
         return n
 
-    def face_pack(self, u, x, fmt: Format, out_parity, dagger=False, nrhs=1, lo=None, hi=None):
-        """(send_lo, send_hi) for a hop to out_parity from x."""
-        lo = torch.empty(self.face_bytes(fmt, nrhs), dtype=torch.uint8, device=x.device) if lo is None else lo
-        hi = torch.empty(self.face_bytes(fmt, nrhs), dtype=torch.uint8, device=x.device) if hi is None else hi
-        W.check(W.wilson_eo_face_pack(self.c, fmt.c, int(out_parity), int(bool(dagger)), _ptr(u), _ptr(x),
-                                      _ptr(lo), _ptr(hi), int(nrhs), _stream()), "wilson_eo_face_pack")
+    def face_pack(self, u, x, fmt: Format, out_parity, dagger=False, nrhs=1, lo=None, hi=None, mu=3):
+        """(send_lo, send_hi) of direction mu for a hop to out_parity from x."""
+        nb = self.face_bytes(fmt, nrhs, mu)
+        lo = torch.empty(nb, dtype=torch.uint8, device=x.device) if lo is None else lo
+        hi = torch.empty(nb, dtype=torch.uint8, device=x.device) if hi is None else hi
+        W.check(W.wilson_eo_face_pack(self.c, fmt.c, int(mu), int(out_parity), int(bool(dagger)), _ptr(u),
+                                      _ptr(x), _ptr(lo), _ptr(hi), int(nrhs), _stream()), "wilson_eo_face_pack")
         return lo, hi
 
     def face_unpack(self, u, recv_lo, recv_hi, out, fmt: Format, out_parity, dagger=False,
-                    phase_lo=1.0, phase_hi=1.0, alpha=1.0, nrhs=1):
-        """Adds the received faces to out (in place)."""
+                    phase_lo=1.0, phase_hi=1.0, alpha=1.0, nrhs=1, mu=3):
+        """Adds the received faces of direction mu to out (in place)."""
         pl = (ctypes.c_double * 2)(complex(phase_lo).real, complex(phase_lo).imag)
         phh = (ctypes.c_double * 2)(complex(phase_hi).real, complex(phase_hi).imag)
-        W.check(W.wilson_eo_face_unpack(self.c, fmt.c, int(out_parity), int(bool(dagger)), pl, phh,
+        W.check(W.wilson_eo_face_unpack(self.c, fmt.c, int(mu), int(out_parity), int(bool(dagger)), pl, phh,
                                         float(alpha), _ptr(u), _ptr(recv_lo), _ptr(recv_hi), _ptr(out),
                                         int(nrhs), _stream()), "wilson_eo_face_unpack")
         return out

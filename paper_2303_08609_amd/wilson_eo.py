@@ -77,10 +77,10 @@ _SIGS = {
                                 _vp, C.c_int, _vp]),
     "wilson_eo_hop_axpy": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int, C.c_double,
                                      _vp, _vp, _vp, _vp, C.c_int, _vp]),
-    "weo_face_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format), C.c_int]),
-    "wilson_eo_face_pack": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int, _vp, _vp,
-                                      _vp, _vp, C.c_int, _vp]),
-    "wilson_eo_face_unpack": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int,
+    "weo_face_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int]),
+    "wilson_eo_face_pack": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int, C.c_int, _vp,
+                                      _vp, _vp, _vp, C.c_int, _vp]),
+    "wilson_eo_face_unpack": (C.c_int, [_P(weo_lattice), _P(weo_format), C.c_int, C.c_int, C.c_int,
                                         _P(C.c_double), _P(C.c_double), C.c_double, _vp, _vp, _vp,
                                         _vp, C.c_int, _vp]),
     "weo_clover_bytes": (C.c_size_t, [_P(weo_lattice), _P(weo_format)]),

@@ -133,27 +133,33 @@ def test_autograd_solve_raises_on_unconverged_status(monkeypatch):
 
 
 def test_face_sizes_and_validation_without_gpu():
-    lat = W.make_lattice((32, 32, 32, 8), 0.126)
-    nf = 32 ** 3 // 2                     # sites of one parity in a t slice
+    lat = W.make_lattice((16, 8, 12, 8), 0.126)
+    lx, ly, lz, lt = 16, 8, 12, 8
+    nfs = {0: ly * lz * lt // 2, 1: lx // 2 * lz * lt, 2: lx // 2 * ly * lt, 3: lx // 2 * ly * lz}
     for (sp, lp), cb in (((W.WEO_F64, W.WEO_F64), 16), ((W.WEO_F32, W.WEO_F32), 8),
                          ((W.WEO_F16, W.WEO_F16), 4), ((W.WEO_BF16, W.WEO_F16), 4)):
         f = W.make_format(sp, lp, W.WEO_LINK12)
-        assert W.weo_face_bytes(lat, f, 1) == nf * 6 * cb
-        assert W.weo_face_bytes(lat, f, 12) == 12 * nf * 6 * cb
-        assert W.weo_face_bytes(lat, f, 0) == 0
+        for mu, nf in nfs.items():
+            assert W.weo_face_bytes(lat, f, mu, 1) == nf * 6 * cb
+            assert W.weo_face_bytes(lat, f, mu, 12) == 12 * nf * 6 * cb
+            assert W.weo_face_bytes(lat, f, mu, 0) == 0
+        assert W.weo_face_bytes(lat, f, 4, 1) == 0 and W.weo_face_bytes(lat, f, -1, 1) == 0
     f = W.make_format(W.WEO_F32)
     a, b, c, d = 1 << 28, 2 << 28, 3 << 28, 4 << 28     # fake aligned, disjoint
     one = (C.c_double * 2)(1.0, 0.0)
     nan = (C.c_double * 2)(float("nan"), 0.0)
-    assert W.wilson_eo_face_pack(lat, f, 1, 0, a, b, c, c, 1, None) == W.WEO_ERR_ARG   # lo == hi
-    assert W.wilson_eo_face_pack(lat, f, 1, 0, a, b, b, d, 1, None) == W.WEO_ERR_ARG   # lo over in
-    assert W.wilson_eo_face_pack(lat, f, 2, 0, a, b, c, d, 1, None) == W.WEO_ERR_ARG
-    assert W.wilson_eo_face_pack(lat, f, 1, 0, a, b + 64, c, d, 1, None) == W.WEO_ERR_ALIGN
-    assert W.wilson_eo_face_unpack(lat, f, 1, 0, nan, one, 1.0, a, b, c, d, 1, None) == W.WEO_ERR_ARG
-    assert W.wilson_eo_face_unpack(lat, f, 1, 0, None, one, 1.0, a, b, c, d, 1, None) == W.WEO_ERR_ARG
-    assert W.wilson_eo_face_unpack(lat, f, 1, 0, one, one, float("inf"), a, b, c, d, 1,
-                                   None) == W.WEO_ERR_ARG
-    assert W.wilson_eo_face_unpack(lat, f, 1, 0, one, one, 1.0, a, b, c, b, 1, None) == W.WEO_ERR_ARG
+    for mu in range(4):
+        assert W.wilson_eo_face_pack(lat, f, mu, 1, 0, a, b, c, c, 1, None) == W.WEO_ERR_ARG   # lo == hi
+        assert W.wilson_eo_face_pack(lat, f, mu, 1, 0, a, b, b, d, 1, None) == W.WEO_ERR_ARG   # lo over in
+        assert W.wilson_eo_face_pack(lat, f, mu, 2, 0, a, b, c, d, 1, None) == W.WEO_ERR_ARG
+        assert W.wilson_eo_face_pack(lat, f, mu, 1, 0, a, b + 64, c, d, 1, None) == W.WEO_ERR_ALIGN
+        assert W.wilson_eo_face_unpack(lat, f, mu, 1, 0, nan, one, 1.0, a, b, c, d, 1, None) == W.WEO_ERR_ARG
+        assert W.wilson_eo_face_unpack(lat, f, mu, 1, 0, None, one, 1.0, a, b, c, d, 1, None) == W.WEO_ERR_ARG
+        assert W.wilson_eo_face_unpack(lat, f, mu, 1, 0, one, one, float("inf"), a, b, c, d, 1,
+                                       None) == W.WEO_ERR_ARG
+        assert W.wilson_eo_face_unpack(lat, f, mu, 1, 0, one, one, 1.0, a, b, c, b, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_face_pack(lat, f, 4, 1, 0, a, b, c, d, 1, None) == W.WEO_ERR_ARG
+    assert W.wilson_eo_face_unpack(lat, f, -1, 1, 0, one, one, 1.0, a, b, c, d, 1, None) == W.WEO_ERR_ARG
 
 
 def test_header_constants_match_the_binding():

@@ -1,4 +1,4 @@
-"""A hop split along t (the one-device share of the domain decomposition of
+"""A hop split along one or more directions (the one-device share of the domain decomposition of
 Sec. 3.6 and 4.1): each slab of consecutive t slices runs the bulk hop with
 a zero t phase, packs its two t faces, and adds the faces received from its
 neighbours.  Checked against the oracle's hop of the whole lattice for the
@@ -146,3 +146,117 @@ def test_slabs_multi_rhs():
     for r in range(3):
         want = W.hop_eo(u_or, psi_or[r], 0, np.array(bc, dtype=complex))
         assert rel_err(got[r], want) <= TOL["f32"], r
+
+
+# ---- splits along any set of directions ------------------------------------------
+
+class Grid:
+    """The lattice cut into n[mu] blocks along each direction mu (a process
+    grid); each block holds its own packed links and fields and runs the bulk
+    hop with zero phases in every direction in ``dirs`` (the exchanged ones),
+    then packs, exchanges and unpacks the faces of those directions.  A
+    direction in ``dirs`` with n[mu] = 1 exchanges with itself (the paper's
+    forced communication)."""
+
+    def __init__(self, dims, fmt, u, bc, n, dirs):
+        self.dims, self.fmt, self.bc, self.n, self.dirs = dims, fmt, bc, n, tuple(dirs)
+        self.ld = tuple(dims[m] // n[m] for m in range(4))
+        assert all(dims[m] % n[m] == 0 and self.ld[m] % 2 == 0 for m in range(4))
+        self.idx = [(ix, iy, iz, it) for it in range(n[3]) for iz in range(n[2]) for iy in range(n[1])
+                    for ix in range(n[0])]
+        self.lat = {i: Lattice(self.ld, KAPPA, bc) for i in self.idx}
+        self.u = {i: self.lat[i].pack_gauge(to_device(np.ascontiguousarray(u[(slice(None),) + self._sl(i)])), fmt)
+                  for i in self.idx}
+
+    def _sl(self, i, half=False):
+        """Slices [t][z][y][x] (x halved for one-parity arrays) of block i."""
+        lx, ly, lz, lt = self.ld
+        ix, iy, iz, it = i
+        xs = slice(ix * lx // 2, (ix + 1) * lx // 2) if half else slice(ix * lx, (ix + 1) * lx)
+        return (slice(it * lt, (it + 1) * lt), slice(iz * lz, (iz + 1) * lz), slice(iy * ly, (iy + 1) * ly), xs)
+
+    def pack(self, psi_half):
+        return {i: self.lat[i].pack_spinor(to_device(np.ascontiguousarray(psi_half[self._sl(i, True)])), self.fmt)
+                for i in self.idx}
+
+    def hop(self, x, out_parity, dagger):
+        outs, faces = {}, {}
+        for i in self.idx:
+            outs[i] = self.lat[i].open_dirs(self.dirs).hop(self.u[i], x[i], self.fmt, out_parity, dagger)
+            for mu in self.dirs:
+                faces[i, mu] = self.lat[i].face_pack(self.u[i], x[i], self.fmt, out_parity, dagger, mu=mu)
+        for i in self.idx:
+            for mu in self.dirs:
+                below = tuple((c - 1) % self.n[m] if m == mu else c for m, c in enumerate(i))
+                above = tuple((c + 1) % self.n[m] if m == mu else c for m, c in enumerate(i))
+                self.lat[i].face_unpack(self.u[i], faces[below, mu][1], faces[above, mu][0], outs[i], self.fmt,
+                                        out_parity, dagger, mu=mu,
+                                        phase_lo=self.bc[mu] if i[mu] == 0 else 1.0,
+                                        phase_hi=self.bc[mu] if i[mu] == self.n[mu] - 1 else 1.0)
+        return outs
+
+    def gather(self, outs):
+        lx, ly, lz, lt = self.dims
+        full = np.zeros((lt, lz, ly, lx // 2, 4, 3), dtype=np.complex128)
+        for i in self.idx:
+            full[self._sl(i, True)] = self.lat[i].unpack_spinor(outs[i], self.fmt).cpu().numpy()
+        return full
+
+
+CPH = tuple(np.exp(1j * np.array([0.4, -1.1, 2.0, 2.9])))
+
+
+@pytest.mark.parametrize("fmt_t", FORMATS, ids=lambda f: f"{f[0]}-{f[1]}-{f[2]}")
+def test_forced_exchange_in_all_four_directions(fmt_t):
+    """One block = the whole lattice with every direction's faces sent to
+    itself (the communication the paper forces in all four directions for
+    its single-node runs): bulk hop with all four phases zero plus the x, y,
+    z and t faces equals the oracle's hop, both parities, with and without
+    dagger, complex boundary phases."""
+    dims = (4, 6, 2, 8)
+    print(f"forced exchange x,y,z,t fmt={fmt_t}", flush=True)
+    u, psi, u_or, psi_or = _inputs(dims, fmt_t, 1401)
+    fmt = Format(*fmt_t)
+    grid = Grid(dims, fmt, u, CPH, (1, 1, 1, 1), (0, 1, 2, 3))
+    x = grid.pack(psi)
+    for par in (0, 1):
+        for dag in (False, True):
+            got = grid.gather(grid.hop(x, par, dag))
+            want = W.hop_eo(u_or, psi_or, 1 - par, np.array(CPH), dagger=dag)
+            assert rel_err(got, want) <= TOL[fmt_t[0]], (par, dag, rel_err(got, want))
+
+
+@pytest.mark.parametrize("n", [(1, 1, 2, 2), (2, 1, 1, 2), (2, 2, 1, 1), (4, 1, 1, 1), (2, 2, 2, 2)],
+                         ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("fmt_t", [("f64", "f64", 18), ("f32", "f32", 12)], ids=["f64", "f32-12"])
+def test_block_grids_match_oracle(fmt_t, n):
+    """The lattice cut into a grid of blocks (the paper's process grid
+    [1,1,2,2], x splits across the even-odd compacted direction, all four
+    directions at once); each block's faces go to its neighbours, every
+    other direction exchanges with itself.  The gathered hop equals the
+    oracle's hop of the whole lattice."""
+    dims = (8, 4, 4, 8)
+    print(f"block grid {n} fmt={fmt_t}", flush=True)
+    u, psi, u_or, psi_or = _inputs(dims, fmt_t, 1411)
+    fmt = Format(*fmt_t)
+    grid = Grid(dims, fmt, u, CPH, n, (0, 1, 2, 3))
+    x = grid.pack(psi)
+    for par in (0, 1):
+        for dag in (False, True):
+            got = grid.gather(grid.hop(x, par, dag))
+            want = W.hop_eo(u_or, psi_or, 1 - par, np.array(CPH), dagger=dag)
+            assert rel_err(got, want) <= TOL[fmt_t[0]], (par, dag, rel_err(got, want))
+
+
+def test_split_only_some_directions():
+    """A 2 x 2 grid in z and t with x and y left to the bulk hop (their phases
+    kept): only the split directions exchange faces."""
+    dims = (4, 4, 4, 8)
+    print("z,t split only", flush=True)
+    fmt_t = ("f32", "f32", 18)
+    u, psi, u_or, psi_or = _inputs(dims, fmt_t, 1421)
+    grid = Grid(dims, Format(*fmt_t), u, CPH, (1, 1, 2, 2), (2, 3))
+    x = grid.pack(psi)
+    got = grid.gather(grid.hop(x, 1, False))
+    want = W.hop_eo(u_or, psi_or, 0, np.array(CPH))
+    assert rel_err(got, want) <= 1e-6
