@@ -134,6 +134,9 @@ def main():
     ap.add_argument("--solve-inner", default="f16/f16/12", help="inner format of --profile-solve")
     ap.add_argument("--solve-method", default="bicgstab", choices=["cg", "bicgstab", "blockcg"],
                     help="inner method of --profile-solve")
+    ap.add_argument("--profile-split", action="store_true",
+                    help="short fixed run for rocprofv3: one device's share of the t-split hop at "
+                         "32^3x8, sequential and with the face pack on a second stream, --steps each")
     ap.add_argument("--profile-mode", action="store_true",
                     help="short fixed run for rocprofv3: a 1 GiB device copy (counter "
                          "calibration) and --steps hop launches per format, nothing else")
@@ -162,6 +165,32 @@ def main():
             torch.cuda.synchronize()
             print(f"[bench] profiled 12-rhs solve {k}: {info['seconds']:.4f} s, inner {info['iters']}, "
                   f"outer {info['outer_iters']}", file=sys.stderr, flush=True)
+        return
+    if a.profile_split:
+        sdims = (32, 32, 32, 8)
+        slat = Lattice(sdims, KAPPA, (1, 1, 1, -1))
+        sopen = slat.open_t()
+        f2 = Format("f32", "f32", 18)
+        ud = slat.pack_gauge(to_device(inputs.gen_gauge(sdims, EPS, SEED_GAUGE)), f2)
+        xd = slat.pack_spinor(to_device(inputs.gen_spinor_half(sdims, SEED_SRC)), f2)
+        out = slat.new_spinor(f2)
+        lo, hi = slat.face_pack(ud, xd, f2, 1)
+        stream = torch.cuda.current_stream()
+        side = torch.cuda.Stream()
+        for mode in ("sequential", "overlapped"):
+            for _ in range(a.steps):
+                if mode == "sequential":
+                    slat.face_pack(ud, xd, f2, 1, lo=lo, hi=hi)
+                    sopen.hop(ud, xd, f2, 1, out=out)
+                else:
+                    side.wait_stream(stream)
+                    with torch.cuda.stream(side):
+                        slat.face_pack(ud, xd, f2, 1, lo=lo, hi=hi)
+                    sopen.hop(ud, xd, f2, 1, out=out)
+                    stream.wait_stream(side)
+                slat.face_unpack(ud, hi, lo, out, f2, 1, phase_lo=-1.0, phase_hi=-1.0)
+            torch.cuda.synchronize()
+            print(f"[bench] profiled {a.steps} t-split hops ({mode})", file=sys.stderr, flush=True)
         return
     lat = Lattice(DIMS, KAPPA, (1, 1, 1, -1))
     v = lat.volume
