@@ -335,6 +335,242 @@ __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
     }
 }
 
+// ---- link-resident form on packed FP16 pairs (FP16 spinors and links) --------
+// The FP32 form above converts every FP16 word it reads (8 links and 8
+// neighbour records per site and right-hand side) and spends 4 FP32
+// instructions per complex multiply-add; measured, it issues VALU work on
+// about 90 % of the cycles, so arithmetic, not memory, bounds it.  Here the
+// values stay FP16 pairs (re, im) where they are read: the spin projection
+// is one packed FP16 add per complex number, and the SU(3) products are
+// v_dot2_f32_f16 (two FP16 products summed into an FP32 accumulator), two
+// per complex multiply-add:
+//     (U h).re = dot2((U.re, U.im), (h.re, -h.im)),  (U h).im = dot2(U, (h.im, h.re))
+//     (U^dag h).re = dot2(U, h),                      (U^dag h).im = dot2(U, (h.im, -h.re))
+// with accumulation and the reconstruction in FP32.  A site's 8 links are
+// kept as 9 FP16 pairs each (a 12-real link's third row rebuilt once per
+// site in FP32 and rounded to FP16; boundary phases folded in once per
+// site).  The projected half spinor and the rebuilt row are rounded to FP16
+// (relative 2^-11, the storage precision of the inputs); products and sums
+// are FP32.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2v h2v_of(uint32_t w) { return __builtin_bit_cast(h2v, w); }
+__device__ __forceinline__ uint32_t u32_of(h2v v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2(h2v_of(a), h2v_of(b), c, false);
+}
+__device__ __forceinline__ uint32_t swap_pair(uint32_t w) { return __builtin_amdgcn_alignbit(w, w, 16); }
+
+struct Link16 {
+    uint32_t e[9];       // U_ab as FP16 pairs, row-major
+};
+
+// Link of direction k of the site (raw FP16 words), third row rebuilt for
+// 12 reals, boundary phase ph folded in on edge hops (ph U forward,
+// (ph U)^dag = conj(ph) U^dag backward, so the stored link is ph U either way).
+template <bool L12, bool CPH>
+__device__ __forceinline__ void link16_load(const uint8_t* base, uint32_t n, uint32_t i, bool edge, float2 ph,
+                                            Link16& L) {
+    RawRec<P_F16, L12 ? 6 : 9, true> r;
+    r.load(base, n, i);
+    constexpr int NW = L12 ? 6 : 9;
+    uint32_t w[9];
+#pragma unroll
+    for (int p = 0; p < Rec<P_F16, NW>::NFULL; ++p) {
+        w[4 * p] = r.w[p].x; w[4 * p + 1] = r.w[p].y; w[4 * p + 2] = r.w[p].z; w[4 * p + 3] = r.w[p].w;
+    }
+    if constexpr (Rec<P_F16, NW>::TAILB == 8) { w[4 * Rec<P_F16, NW>::NFULL] = r.t8.x; w[4 * Rec<P_F16, NW>::NFULL + 1] = r.t8.y; }
+    if constexpr (Rec<P_F16, NW>::TAILB == 4) w[4 * Rec<P_F16, NW>::NFULL] = r.t4;
+    if constexpr (L12) {
+        float2 u[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u[k] = h2_to_f2(w[k]);
+        w[6] = f2_to_h2(conj_(sub(mul(u[1], u[5]), mul(u[2], u[4]))));
+        w[7] = f2_to_h2(conj_(sub(mul(u[2], u[3]), mul(u[0], u[5]))));
+        w[8] = f2_to_h2(conj_(sub(mul(u[0], u[4]), mul(u[1], u[3]))));
+    }
+    if constexpr (CPH) {
+        const float2 f = edge ? ph : make_float2(1.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) L.e[k] = f2_to_h2(mul(f, h2_to_f2(w[k])));
+    } else {
+        // a real phase +-1: a sign flip of both halves where it is -1
+        const uint32_t flip = (edge && ph.x < 0.f) ? 0x80008000u : 0u;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) L.e[k] = w[k] ^ flip;
+    }
+}
+
+// One direction on a neighbour record p (12 FP16 pairs, [spin][colour]):
+// project with (1 - S gamma_mu), multiply by U (FWD) or U^dag, rebuild and
+// accumulate in FP32 (the rules of hop_dir).
+template <int MU, int S, bool FWD>
+__device__ __forceinline__ void h16_dir(const uint32_t* p, const Link16& L, float2* acc) {
+    uint32_t h[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const h2v p0 = h2v_of(p[c]), p1 = h2v_of(p[3 + c]), p2 = h2v_of(p[6 + c]), p3 = h2v_of(p[9 + c]);
+        h2v h0, h1;
+        if constexpr (MU == 0) {
+            const h2v i3 = h2v{-p3.y, p3.x}, i2 = h2v{-p2.y, p2.x};
+            h0 = S > 0 ? p0 + i3 : p0 - i3;
+            h1 = S > 0 ? p1 + i2 : p1 - i2;
+        } else if constexpr (MU == 1) {
+            h0 = S > 0 ? p0 + p3 : p0 - p3;
+            h1 = S > 0 ? p1 - p2 : p1 + p2;
+        } else if constexpr (MU == 2) {
+            const h2v i2 = h2v{-p2.y, p2.x}, i3 = h2v{-p3.y, p3.x};
+            h0 = S > 0 ? p0 + i2 : p0 - i2;
+            h1 = S > 0 ? p1 - i3 : p1 + i3;
+        } else {
+            h0 = S > 0 ? p2 : p0;
+            h1 = S > 0 ? p3 : p1;
+        }
+        h[0][c] = u32_of(h0);
+        h[1][c] = u32_of(h1);
+    }
+    float2 g[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        uint32_t ha[3], hb[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if constexpr (FWD) {
+                ha[b] = h[s][b] ^ 0x80000000u;                    // (h.re, -h.im)
+                hb[b] = swap_pair(h[s][b]);                       // (h.im, h.re)
+            } else {
+                ha[b] = h[s][b];                                  // (h.re, h.im)
+                hb[b] = swap_pair(h[s][b]) ^ 0x80000000u;         // (h.im, -h.re)
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const uint32_t u = FWD ? L.e[3 * a + b] : L.e[3 * b + a];
+                re = dot2(u, ha[b], re);
+                im = dot2(u, hb[b], im);
+            }
+            g[s][a] = make_float2(re, im);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float2 g0 = g[0][a], g1 = g[1][a];
+        if constexpr (MU == 3) {
+            const int o = S > 0 ? 6 : 0;
+            acc[o + a].x = fmaf(2.f, g0.x, acc[o + a].x); acc[o + a].y = fmaf(2.f, g0.y, acc[o + a].y);
+            acc[o + 3 + a].x = fmaf(2.f, g1.x, acc[o + 3 + a].x); acc[o + 3 + a].y = fmaf(2.f, g1.y, acc[o + 3 + a].y);
+        } else {
+            acc[a] = add(acc[a], g0);
+            acc[3 + a] = add(acc[3 + a], g1);
+            if constexpr (MU == 0) {
+                acc[6 + a] = S > 0 ? sub(acc[6 + a], imul(g1)) : add(acc[6 + a], imul(g1));
+                acc[9 + a] = S > 0 ? sub(acc[9 + a], imul(g0)) : add(acc[9 + a], imul(g0));
+            } else if constexpr (MU == 1) {
+                acc[6 + a] = S > 0 ? sub(acc[6 + a], g1) : add(acc[6 + a], g1);
+                acc[9 + a] = S > 0 ? add(acc[9 + a], g0) : sub(acc[9 + a], g0);
+            } else {
+                acc[6 + a] = S > 0 ? sub(acc[6 + a], imul(g0)) : add(acc[6 + a], imul(g0));
+                acc[9 + a] = S > 0 ? add(acc[9 + a], imul(g1)) : sub(acc[9 + a], imul(g1));
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void rec16_words(const RawRec<P_F16, 12>& r, uint32_t* p) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) { p[4 * q] = r.w[q].x; p[4 * q + 1] = r.w[q].y; p[4 * q + 2] = r.w[q].z; p[4 * q + 3] = r.w[q].w; }
+}
+
+template <bool DAG, int D, int K>
+__device__ __forceinline__ void h16_step(const HopParams& P, const uint8_t* in, const uint8_t* in_next,
+                                         const Nbr& nb, const Link16 (&lk)[8], RawRec<P_F16, 12> (&ring)[D + 1],
+                                         float2* acc) {
+    constexpr int MU = K / 2;
+    constexpr int SF = DAG ? -1 : 1;
+    if constexpr (K + D < 8) ring[(K + D) % (D + 1)].load(in, P.g.vh, nb.i[K + D]);
+    else ring[(K + D) % (D + 1)].load(in_next, P.g.vh, nb.i[K + D - 8]);
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t p[12];
+    rec16_words(ring[K % (D + 1)], p);
+    if constexpr ((K & 1) == 0) h16_dir<MU, SF, true>(p, lk[K], acc);
+    else h16_dir<MU, -SF, false>(p, lk[K], acc);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (K + 1 < 8) h16_step<DAG, D, K + 1>(P, in, in_next, nb, lk, ring, acc);
+}
+
+template <bool L12, bool DAG, bool CPH, int D>
+__global__ void __launch_bounds__(256) k_hop_lr16(const MrhsParams M) {
+    static_assert(8 % (D + 1) == 0, "ring size must divide the 8 directions");
+    const HopParams& P = M.h;
+    const uint32_t S = blockDim.x;
+    const uint32_t n = P.g.vh;
+    const uint32_t nchunk = (n + 63) >> 6;
+    for (uint32_t b = blockIdx.x; b < M.nblk; b += gridDim.x) {
+        const uint32_t blk = xcd_block(b, M.nblk, P.remap);
+        const uint32_t base = block_first_site(P.sched, P.g, blk, S);
+        const uint32_t ih = base + threadIdx.x;
+        const bool valid = ih < n;
+        Nbr nb;
+        Link16 lk[8];
+        RawRec<P_F16, 12> ring[D + 1];
+        if (valid) {
+            const Site s = decode(P.g, ih, P.out_par);
+            nb = neighbours(P.g, s);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int mu = k >> 1;
+                const bool fwd = (k & 1) == 0;
+                const float2 ph = make_float2((float)P.ph[mu][0], (float)(fwd ? P.ph[mu][1] : -P.ph[mu][1]));
+                link16_load<L12, CPH>(P.u + (size_t)(2 * mu + (fwd ? P.out_par : 1 - P.out_par)) * P.link_block, n,
+                                      fwd ? ih : nb.i[k], nb.edge[k], ph, lk[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < D; ++k) ring[k].load(P.in, n, nb.i[k]);
+        }
+        for (int r = 0; r < M.nrhs; ++r) {
+            double nrm = 0.0;
+            if (valid) {
+                // keep the link words as they are across the loop
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) asm volatile("" : "+v"(lk[k].e[e]));
+                const uint8_t* in = P.in + (size_t)r * P.spinor_bytes;
+                const uint8_t* in_next = r + 1 < M.nrhs ? in + P.spinor_bytes : in;
+                float2 acc[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = make_float2(0.f, 0.f);
+                h16_step<DAG, D, 0>(P, in, in_next, nb, lk, ring, acc);
+                if (P.y) {
+                    float2 yv[12];
+                    load_rec<P_F16, 12>(P.y + (size_t)r * P.spinor_bytes, n, ih, yv);
+                    const float a = (float)P.alpha;
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        acc[k].x = fmaf(a, acc[k].x, yv[k].x);
+                        acc[k].y = fmaf(a, acc[k].y, yv[k].y);
+                    }
+                }
+                store_rec<P_F16, 12>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
+                if (P.partial) {
+                    float2 st[12];
+                    round_rec<P_F16, 12>(acc, st);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        nrm += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
+                }
+            }
+            if (P.partial) {
+                const double t = wave_sum64(nrm);
+                const uint32_t chunk = (base + (threadIdx.x & ~63u)) >> 6;
+                if ((threadIdx.x & 63) == 0 && chunk < nchunk) P.partial[(size_t)r * nchunk + chunk] = t;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host ----
 static HopParams hop_params(const HopLaunch& h) {
     HopParams P;
@@ -398,6 +634,31 @@ static hipError_t lr_fmt(const HopLaunch& h, const MrhsParams& M, int depth, dim
                       : lr_depth<SP, LP, L12, 1>(h, M, grid, block, s);
 }
 
+template <bool L12, int D>
+static hipError_t lr16_depth(const HopLaunch& h, const MrhsParams& M, dim3 grid, dim3 block, hipStream_t s) {
+    bool cph = false;
+    for (int m = 0; m < 4; ++m) cph = cph || h.phase[m][1] != 0.0;
+#define WEO_LR16(DG, CP) hipLaunchKernelGGL((k_hop_lr16<L12, DG, CP, D>), grid, block, 0, s, M)
+    if (h.dagger) { if (cph) WEO_LR16(true, true); else WEO_LR16(true, false); }
+    else { if (cph) WEO_LR16(false, true); else WEO_LR16(false, false); }
+#undef WEO_LR16
+    return hipGetLastError();
+}
+
+// FP16 spinors with FP16 links: the packed-pair form (ring depth 1 or 3)
+static hipError_t launch_hop_lr16(const HopLaunch& h, const MrhsParams& M, int depth, dim3 grid, dim3 block,
+                                  hipStream_t s) {
+    switch (h.fmt) {
+        case FMT_H_H_18: return depth == 3 ? lr16_depth<false, 3>(h, M, grid, block, s)
+                                           : lr16_depth<false, 1>(h, M, grid, block, s);
+        case FMT_H_H_12: return depth == 3 ? lr16_depth<true, 3>(h, M, grid, block, s)
+                                           : lr16_depth<true, 1>(h, M, grid, block, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool lr16_supported(int fmt) { return fmt == FMT_H_H_18 || fmt == FMT_H_H_12; }
+
 static hipError_t launch_hop_lr(const HopLaunch& h, const MrhsParams& M, int depth, dim3 grid, dim3 block,
                                 hipStream_t s) {
     switch (h.fmt) {
@@ -427,6 +688,9 @@ hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) 
             if (nwg > cap) nwg = cap;
             nwg = ((nwg + 7u) / 8u) * 8u;
         }
+        // nr = -1 / -3: FP32 arithmetic, ring depth 1 / 3; nr = -2 / -4: the
+        // packed FP16 form, ring depth 1 / 3
+        if (c.nr == -2 || c.nr == -4) return launch_hop_lr16(h, M, c.nr == -4 ? 3 : 1, dim3(nwg), dim3((unsigned)c.s), s);
         return launch_hop_lr(h, M, -c.nr, dim3(nwg), dim3((unsigned)c.s), s);
     }
     M.nrhs = h.nrhs;
@@ -478,6 +742,8 @@ std::vector<MrhsCfg> candidates(const HopLaunch& h) {
                 for (int bz : {0, 2, 4, 8}) {
                     if (bz && make_sched(h.g, bz, (uint32_t)s).bz != bz) continue;
                     for (int nr : {-1, -3}) v.push_back({nr, s, persist, bz, 0});
+                    if (lr16_supported(h.fmt))
+                        for (int nr : {-2, -4}) v.push_back({nr, s, persist, bz, 0});
                 }
     const int nrs[] = {2, 3, 4, 6};
     for (int nr : nrs) {
@@ -546,9 +812,9 @@ int set_mrhs_shape(int nr, int sites, int persist, int bz, int split) {
         g_forced = {nr, 0, 0, 0, 0};
         return 0;
     }
-    if (nr < -3 || nr == -2) return -1;
+    if (nr < -4) return -1;
     if (split != 0 && split != 1) return -1;
-    if (nr == -1 || nr == -3) {
+    if (nr < 0) {
         if (sites != 64 && sites != 128 && sites != 256) return -1;
         if (persist != 0 && persist != 1) return -1;
         if (bz < 0 || bz > 64) return -1;
@@ -575,6 +841,11 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
     if (forced.nr == 1) return launch_hop_single(h, s);
     if (forced.nr < 0) {
         if (!lr_supported(h.fmt)) return launch_hop_single(h, s);
+        if ((forced.nr == -2 || forced.nr == -4) && !lr16_supported(h.fmt)) {
+            MrhsCfg c = forced;
+            c.nr = forced.nr == -4 ? -3 : -1;          // FP32 arithmetic for the other formats
+            return launch_hop_mrhs(h, c, s);
+        }
         return launch_hop_mrhs(h, forced, s);
     }
     if (forced.nr > 1) {

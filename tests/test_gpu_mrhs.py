@@ -13,7 +13,7 @@ from tests._helpers import AP, ROUND, link_as_stored, rel_err
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-6, "f16": 2e-3, "bf16": 1e-2}
-SHAPES = [(1, 0, 0, 0, 0)] + [(d, s, p, bz, 0) for d in (-1, -3) for s in (64, 128, 256) for p in (0, 1)
+SHAPES = [(1, 0, 0, 0, 0)] + [(d, s, p, bz, 0) for d in (-1, -2, -3, -4) for s in (64, 128, 256) for p in (0, 1)
                               for bz in (0, 2)] + [(nr, s, p, bz, sp) for nr in (2, 3, 4, 6) for s in (64, 128, 256)
                               for p in (0, 1) for bz in (0, 2) for sp in (0, 1)]
 
@@ -53,6 +53,46 @@ def test_every_shape_matches_oracle(fmt_t, dims):
             got = lat.unpack_spinor(out, fmt, nrhs=nrhs).cpu().numpy()
             for r in range(nrhs):
                 assert rel_err(got[r], ref[r]) <= TOL[fmt_t[0]], (shape, dag, r)
+
+
+PAIR_SHAPES = [(d, s, p, bz, 0) for d in (-2, -4) for s in (64, 128, 256) for p in (0, 1) for bz in (0, 2)]
+
+
+@pytest.mark.parametrize("bc", ["ap", "complex"])
+@pytest.mark.parametrize("fmt_t", [("f16", "f16", 12), ("f16", "f16", 18)], ids=["f16-12", "f16-18"])
+@pytest.mark.parametrize("dims", [(6, 4, 4, 10), (16, 8, 4, 6)], ids=["ragged", "strips"])
+def test_fp16_pair_form_matches_oracle(dims, fmt_t, bc):
+    """The link-resident hop on packed FP16 pairs (dot2 products, FP32
+    accumulation) for FP16 spinors and links: every launch shape, both output
+    parities, dagger, real and complex boundary phases, the axpy epilogue;
+    against the oracle on the rounded inputs within the FP16 bar."""
+    nrhs = 7
+    print(f"fp16 pair form fmt={fmt_t} dims={dims} bc={bc}", flush=True)
+    phases = AP if bc == "ap" else tuple(np.exp(1j * np.array([0.4, -1.1, 2.0, 2.9])))
+    sp, lp, reals = fmt_t
+    fmt = Format(sp, lp, reals)
+    lat = Lattice(dims, 0.126, phases)
+    u = inputs.gen_gauge(dims, 0.5, 720)
+    psi = inputs.gen_spinor_half(dims, 721, nrhs=nrhs)
+    y = inputs.gen_spinor_half(dims, 722, nrhs=nrhs)
+    u_d, x_d, y_d = lat.pack_gauge(to_device(u), fmt), lat.pack_spinor(to_device(psi), fmt), \
+        lat.pack_spinor(to_device(y), fmt)
+    u_o, psi_o, y_o = link_as_stored(u, lp, reals), ROUND[sp](psi), ROUND[sp](y)
+    ph = np.array(phases, dtype=np.complex128)
+    for shape in PAIR_SHAPES:
+        assert WE.weo_set_mrhs_shape(*shape) == WE.WEO_OK
+        for par in (0, 1):
+            for dag in (False, True):
+                out = lat.hop(u_d, x_d, fmt, out_parity=par, dagger=dag, nrhs=nrhs)
+                got = lat.unpack_spinor(out, fmt, nrhs=nrhs).cpu().numpy()
+                for r in range(nrhs):
+                    want = W.hop_eo(u_o, psi_o[r], 1 - par, ph, dagger=dag)
+                    assert rel_err(got[r], want) <= TOL[sp], (shape, par, dag, r, rel_err(got[r], want))
+        out = lat.hop_axpy(u_d, x_d, y_d, fmt, out_parity=1, alpha=-0.3, nrhs=nrhs)
+        got = lat.unpack_spinor(out, fmt, nrhs=nrhs).cpu().numpy()
+        for r in range(nrhs):
+            want = y_o[r] - 0.3 * W.hop_eo(u_o, psi_o[r], 0, ph)
+            assert rel_err(got[r], want) <= TOL[sp], (shape, "axpy", r)
 
 
 @pytest.mark.parametrize("nrhs", [2, 5, 12, 16])
