@@ -522,7 +522,8 @@ __global__ void __launch_bounds__(256) k_hop_lr16(const MrhsParams M) {
             for (int k = 0; k < 8; ++k) {
                 const int mu = k >> 1;
                 const bool fwd = (k & 1) == 0;
-                const float2 ph = make_float2((float)P.ph[mu][0], (float)(fwd ? P.ph[mu][1] : -P.ph[mu][1]));
+                // ph U for both hops: the backward one multiplies by (ph U)^dag
+                const float2 ph = make_float2((float)P.ph[mu][0], (float)P.ph[mu][1]);
                 link16_load<L12, CPH>(P.u + (size_t)(2 * mu + (fwd ? P.out_par : 1 - P.out_par)) * P.link_block, n,
                                       fwd ? ih : nb.i[k], nb.edge[k], ph, lk[k]);
             }
