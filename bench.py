@@ -6,19 +6,24 @@ kernels of the operator.  ``value`` is 1320 * V flop per step over the timed
 steps (GFlop/s), with every input resident in HBM before timing starts.
 
 The JSON line also carries:
+  gflops_1368   the same rate under the 1368 flop/site count (the 1320 count
+                plus the 48 flop of the diagonal a*x+y on 12 complex numbers);
   roofline      the dominant kernel (the hop) against the 8 TB/s HBM peak, its
                 average duration measured here with HIP events on the stream it
-                runs on, and HBM traffic from the committed rocprofv3 counters
-                when they were taken on the current kernel source;
+                runs on, its fraction of a measured 1 GiB device copy, and
+                L2-to-memory traffic from the committed rocprofv3 counters when
+                they were taken on the current kernel source;
   cpu_baseline  the FP64 NumPy oracle timed on a sample of the same workload
-                on this host (single thread);
+                on this host (single thread; CPU model and count stated), and
+                its apply time at 4^4 and 16^3x32;
   variants      the same apply in other storage formats;
   clover        the even-odd operator with site-local D_ee, D_oo blocks (FP32/18
                 and FP16/12) and its mixed-precision solve;
-  t_split_32x32x32x8
-                one device's share of 32^3x64 cut along t into 8 slabs: the
-                slab hop as bulk kernel + face pack + face unpack (faces
-                exchanged with itself) against the slab's periodic hop;
+  t_split_32x32x32x8, grid_2x2x2x2_block_32x32x32x64
+                one device's share of 32^3x64 cut along t into 8 slabs, and of
+                64^3x128 on a 2^4 grid: the block hop as bulk kernel + face
+                pack + face unpack (faces exchanged with itself) against the
+                block's periodic hop, eager and captured as a HIP graph;
   solve         solve times to a true FP64 residual of 1e-10 (and FP32 CGLS to
                 1e-6): FP64 defect correction with FP16/BF16 inner solves
                 against FP32 inner solves, for one source at 32^3x64, twelve
@@ -91,13 +96,15 @@ def traffic_from_profiles(fmt_key):
 
 def cpu_baseline(budget_s=15.0):
     """FP64 oracle M apply on a 32^3x8 slab (1/8 of the workload volume, same
-    per-site work), repeated until ``budget_s`` seconds are used."""
+    per-site work), repeated until ``budget_s`` seconds are used; plus the
+    oracle's apply time (median of three) on the 4^4 and 16^3x32 lattices of
+    the smaller workloads.  One thread (BLAS threads pinned to 1)."""
     from oracle import wilson as W
     from paper_2303_08609_amd import inputs
+    ph = np.array([1, 1, 1, -1], dtype=np.complex128)
     dims = (32, 32, 32, 8)
     u = inputs.gen_gauge(dims, EPS, SEED_GAUGE)
     psi = inputs.gen_spinor_half(dims, SEED_SRC)
-    ph = np.array([1, 1, 1, -1], dtype=np.complex128)
     v = 32 * 32 * 32 * 8
     n, t0 = 0, time.perf_counter()
     while True:
@@ -106,10 +113,138 @@ def cpu_baseline(budget_s=15.0):
         dt = time.perf_counter() - t0
         if dt >= budget_s or n >= 10:
             break
+    sizes = {}
+    for d, kappa, eps in (((4, 4, 4, 4), 0.125, 0.3), ((16, 16, 16, 32), 0.125, 0.5)):
+        us = inputs.gen_gauge(d, eps, 11)
+        ps = inputs.gen_spinor_half(d, 12)
+        runs = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            W.apply_m(us, ps, kappa, ph)
+            runs.append(time.perf_counter() - t1)
+        vs = d[0] * d[1] * d[2] * d[3]
+        med = sorted(runs)[1]
+        sizes["x".join(map(str, d))] = {"apply_seconds": round(med, 5),
+                                        "gflops": round(FLOP_SITE * vs / med / 1e9, 4)}
     return {"value": round(FLOP_SITE * v * n / dt / 1e9, 4), "unit": "GFlop/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{n} oracle M applies on a 32^3x8 slab (1/8 of 32^3x64), FP64 NumPy, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "host_cpu": host_cpu(),
+            "oracle_apply_at": sizes}
+
+
+def split_timings(blat, dirs, ud, xd, fmt, n, warmup, time_loop):
+    """One device's share of a hop split along ``dirs``: the block's hop with
+    those directions open (bulk), the faces packed in each open direction and
+    added back after a self-exchange (periodic wrap: the block is its own
+    neighbour), in microseconds per hop; eager launches, the face pack on a
+    second stream, and the whole sequence captured as one HIP graph (both
+    orders).  Every graph replay is checked bit for bit against the eager
+    result first."""
+    import torch
+    bopen = blat.open_dirs(dirs)
+    out = blat.new_spinor(fmt)
+    bufs = {mu: blat.face_pack(ud, xd, fmt, 1, mu=mu) for mu in dirs}
+
+    def pack():
+        for mu in dirs:
+            blat.face_pack(ud, xd, fmt, 1, lo=bufs[mu][0], hi=bufs[mu][1], mu=mu)
+
+    def unpack():
+        for mu in dirs:
+            ph = blat.bc[mu]
+            blat.face_unpack(ud, bufs[mu][1], bufs[mu][0], out, fmt, 1, phase_lo=ph, phase_hi=ph, mu=mu)
+
+    plain = lambda: blat.hop(ud, xd, fmt, 1, out=out)
+    bulk = lambda: bopen.hop(ud, xd, fmt, 1, out=out)
+    side = torch.cuda.Stream()          # default priority
+
+    def whole():
+        pack()
+        bulk()
+        unpack()
+
+    def overlapped():
+        # faces packed on a second stream while the bulk kernel runs, as a
+        # sharded hop posts them before its interior work
+        cur = torch.cuda.current_stream()
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            pack()
+        bulk()
+        cur.wait_stream(side)
+        unpack()
+
+    plain()
+    want = blat.unpack_spinor(out, fmt)
+    whole()
+    torch.cuda.synchronize()
+    ref = out.clone()
+    # the faces are added after the bulk sum: equal to the periodic hop up
+    # to the storage format's rounding
+    err = (torch.linalg.vector_norm(blat.unpack_spinor(ref, fmt) - want) / torch.linalg.vector_norm(want)).item()
+    if err > {"f64": 1e-12, "f32": 1e-6}.get(fmt.spinor, 2e-2):
+        raise RuntimeError(f"split hop over {dirs} differs from the periodic hop by {err:.2e}")
+    graphs = {}
+    for name, fn in (("graph_pack_bulk_unpack_us", whole), ("graph_overlapped_us", overlapped)):
+        fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        for _ in range(3):
+            out.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            if not torch.equal(out, ref):
+                raise RuntimeError(f"graph replay of the split hop over {dirs} differs")
+        graphs[name] = g
+    r = {}
+    for name, fn in (("periodic_hop_us", plain), ("bulk_hop_us", bulk), ("face_pack_us", pack),
+                     ("face_unpack_us", unpack), ("pack_bulk_unpack_us", whole),
+                     ("pack_overlapped_bulk_unpack_us", overlapped),
+                     ("graph_pack_bulk_unpack_us", graphs["graph_pack_bulk_unpack_us"].replay),
+                     ("graph_overlapped_us", graphs["graph_overlapped_us"].replay)):
+        for _ in range(warmup):
+            fn()
+        r[name] = round(time_loop(fn, n) * 1e3, 2)
+    r["face_bytes_each_direction"] = {str(mu): blat.face_bytes(fmt, mu=mu) for mu in dirs}
+    del graphs
+    return r
+
+
+def copy_gbs(time_loop, nbytes=1 << 30):
+    """Read+write bandwidth of a plain device copy of ``nbytes`` (the torch
+    D2D copy and a float4-wide elementwise kernel; the faster one is the
+    practical ceiling a streaming kernel can reach)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    res = {}
+    for name, fn in (("memcpy", lambda: dst.copy_(src)),
+                     ("elementwise", lambda: torch.mul(src, 1.0, out=dst))):
+        for _ in range(3):
+            fn()
+        ms = time_loop(fn, 20)
+        res[name] = round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    return res
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 def parse_fmt(s):
@@ -271,6 +406,9 @@ def main():
     achieved = hop_bytes / (ms_hop * 1e-3) / 1e9
     fmt_key = "/".join(map(str, fs))
     traffic = traffic_from_profiles(fmt_key)
+    copy = copy_gbs(time_loop)
+    copy_best = max(copy.values())
+    print(f"[bench] device copy GB/s: {copy}", file=sys.stderr, flush=True)
 
     variants = {}
     for vs in [s for s in a.variants.split(",") if s]:
@@ -286,54 +424,32 @@ def main():
         }
         print(f"[bench] {vs}: {variants[vs]}", file=sys.stderr, flush=True)
 
-    # one device's share of a t-split 32^3x64 lattice over 8 devices: the
-    # 32^3x8 slab hop as bulk (zero t phase) + face pack + face unpack,
-    # against the same slab's periodic hop
+    # one device's share of a t-split 32^3x64 lattice over 8 devices (a
+    # 32^3x8 slab, t open) and of 64^3x128 over a 2^4 grid (a 32^3x64 block,
+    # every direction open): bulk hop + face pack + face unpack with the
+    # faces exchanged with itself, against the block's periodic hop; eager
+    # and as one captured HIP graph
     split = {}
     sdims = (32, 32, 32, 8)
     slat = Lattice(sdims, KAPPA, (1, 1, 1, -1))
-    sopen = slat.open_t()
     su = to_device(inputs.gen_gauge(sdims, EPS, SEED_GAUGE))
     spsi = to_device(inputs.gen_spinor_half(sdims, SEED_SRC))
     for vs in ("f32/f32/18", "f16/f16/12"):
         f2 = Format(*parse_fmt(vs))
         ud = slat.pack_gauge(su, f2)
         xd = slat.pack_spinor(spsi, f2)
-        out = slat.new_spinor(f2)
-        lo, hi = slat.face_pack(ud, xd, f2, 1)
-        n = max(a.steps // 4, 1)
-        plain = lambda: slat.hop(ud, xd, f2, 1, out=out)
-        bulk = lambda: sopen.hop(ud, xd, f2, 1, out=out)
-        pack = lambda: slat.face_pack(ud, xd, f2, 1, lo=lo, hi=hi)
-        unpack = lambda: slat.face_unpack(ud, hi, lo, out, f2, 1, phase_lo=-1.0, phase_hi=-1.0)
-
-        def whole():
-            pack()
-            bulk()
-            unpack()
-        side = torch.cuda.Stream()          # default priority
-
-        def overlapped():
-            # faces packed on a second stream while the bulk kernel runs, as
-            # a sharded hop would post them before its interior work
-            side.wait_stream(stream)
-            with torch.cuda.stream(side):
-                pack()
-            bulk()
-            stream.wait_stream(side)
-            unpack()
-        r = {}
-        for name, fn in (("periodic_hop_us", plain), ("bulk_hop_us", bulk), ("face_pack_us", pack),
-                         ("face_unpack_us", unpack), ("pack_bulk_unpack_us", whole),
-                         ("pack_overlapped_bulk_unpack_us", overlapped)):
-            for _ in range(a.warmup):
-                fn()
-            r[name] = round(time_loop(fn, n) * 1e3, 2)
-        r["face_bytes_each"] = slat.face_bytes(f2)
-        split[vs] = r
-        print(f"[bench] t-split 32^3x8 {vs}: {r}", file=sys.stderr, flush=True)
-        del ud, xd, out, lo, hi
+        split[vs] = split_timings(slat, (3,), ud, xd, f2, max(a.steps // 4, 1), a.warmup, time_loop)
+        print(f"[bench] t-split 32^3x8 {vs}: {split[vs]}", file=sys.stderr, flush=True)
+        del ud, xd
     del su, spsi
+    grid4 = {}
+    for vs in ("f32/f32/18", "f16/f16/12"):
+        f2 = Format(*parse_fmt(vs))
+        ud = lat.pack_gauge(u_dev64, f2)
+        xd = lat.pack_spinor(psi_dev64, f2)
+        grid4[vs] = split_timings(lat, (0, 1, 2, 3), ud, xd, f2, max(a.steps // 4, 1), a.warmup, time_loop)
+        print(f"[bench] 2^4 grid, 32^3x64 block {vs}: {grid4[vs]}", file=sys.stderr, flush=True)
+        del ud, xd
 
     # clover-type operator (site-local D_ee, D_oo): the same lattice with
     # random Hermitian site blocks near 1, packed as inverses
@@ -400,13 +516,20 @@ def main():
                    "apply_bytes_per_site": apply_bytes_per_site(*fs),
                    "apply_frac_hbm": round(apply_bytes_per_site(*fs) * v / (ms_apply * 1e-3) / 1e9
                                            / HBM_PEAK_GBS, 4)},
+        "gflops_1368": round(gflops * 1368 / FLOP_SITE, 1),
         "roofline": {"bound": "hbm", "kernel": "k_hop (one hopping block, V/2 output sites)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_kind": "L2-to-memory bytes per launch (TCC FETCH_SIZE + WRITE_SIZE, "
+                                     "scaled by a 1 GiB copy's reading); null when the kernel "
+                                     "source changed since they were taken",
                      "hop_us": round(ms_hop * 1e3, 2),
-                     "bytes_per_launch": hop_bytes},
+                     "bytes_per_launch": hop_bytes,
+                     "copy_gbs": copy,
+                     "frac_of_copy": round(achieved / copy_best, 4)},
         "variants": variants,
         "t_split_32x32x32x8": split,
+        "grid_2x2x2x2_block_32x32x32x64": grid4,
         "clover": clover,
     }
     if solve is not None:
