@@ -127,7 +127,13 @@ int weo_set_mrhs_shape(int nr, int sites, int persist, int bz, int split);
  * 2 norm partials); returns the untruncated length.  buf may be NULL to
  * query the length.  A multi-rhs launch is tuned on its first call by
  * timing every candidate shape on the caller's stream and buffers, except
- * an in-place axpy (y is out), which runs untuned. */
+ * an in-place axpy (y is out), which runs untuned.  With the environment
+ * variable WILSON_EO_TUNE_CACHE naming a file, tuned shapes are appended to
+ * it (a header line with the cache version and GPU architecture, then one
+ * text line per key) and read back by later processes, which then skip the
+ * timing for those keys; an entry whose shape is not a current candidate
+ * for its key is ignored, and a file with another header is rewritten.
+ * WEO_TUNE=0 disables tuning (and the cache). */
 int weo_tuning_report(char* buf, size_t len);
 
 /* Bytes of the packed gauge field (all 4V links) in format fmt; 0 on error. */

@@ -5,7 +5,7 @@ instructions disabled; host-only sources (``csrc/*.cpp``) by g++ against the
 HIP runtime headers.  Objects go to ``_build/`` at the repository root and the
 library to ``paper_2303_08609_amd/libwilson_eo.so``.  Every call recompiles.
 
-    python -m paper_2303_08609_amd.build [--jobs N] [--debug]
+    python -m paper_2303_08609_amd.build [--jobs N] [--debug] [--sanitize]
 """
 from __future__ import annotations
 
@@ -81,6 +81,32 @@ def build(jobs: int | None = None, debug: bool = False, verbose: bool = False,
     return lib
 
 
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                  "-g", "-O1"]
+
+
+def build_sanitized(jobs: int | None = None, out: str | None = None) -> str:
+    """A CPU-side checking build: the host-only sources (argument checking,
+    solver drivers, workspace layout) compiled by g++ with AddressSanitizer
+    and UndefinedBehaviorSanitizer, linked with the HIP objects of the last
+    regular build (built first if missing; the device code is not
+    instrumented).  Load it with libasan and libubsan preloaded."""
+    hip, cpp = sources()
+    if not all(os.path.exists(os.path.join(BUILD, f + ".o")) for f in hip):
+        build(jobs)
+    objs = [os.path.join(BUILD, f + ".o") for f in hip]
+    cmds = []
+    for f in cpp:
+        o = os.path.join(BUILD, f + ".san.o")
+        objs.append(o)
+        cmds.append(["g++"] + CXX_FLAGS + SANITIZE_FLAGS + ["-c", os.path.join(CSRC, f), "-o", o])
+    with ThreadPoolExecutor(jobs or min(8, os.cpu_count() or 1)) as ex:
+        list(ex.map(_run, cmds))
+    lib = out or os.path.join(BUILD, "libwilson_eo_san.so")
+    _run(["g++", "-shared", "-fPIC"] + SANITIZE_FLAGS + ["-o", lib] + objs + [f"-L{ROCM}/lib", "-lamdhip64"])
+    return lib
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
@@ -89,8 +115,13 @@ def main(argv=None):
     ap.add_argument("-D", dest="defines", action="append", default=[],
                     help="extra preprocessor definition for the HIP sources, e.g. -D WEO_NT_LINKS=1")
     ap.add_argument("--out", default=None, help="library path (default: in the package)")
+    ap.add_argument("--sanitize", action="store_true",
+                    help="build _build/libwilson_eo_san.so: host sources under ASan + UBSan (CPU checks)")
     a = ap.parse_args(argv)
-    print(build(a.jobs, a.debug, a.verbose, tuple(a.defines), a.out))
+    if a.sanitize:
+        print(build_sanitized(a.jobs, a.out))
+    else:
+        print(build(a.jobs, a.debug, a.verbose, tuple(a.defines), a.out))
 
 
 if __name__ == "__main__":

@@ -21,9 +21,11 @@
 // then cached for the life of the process.  The candidates also cover the
 // workgroup schedule (z-strips of 2, 4 or 8 planes, make_sched), which keeps
 // the +-t neighbours of 12 fields inside L2.  WEO_TUNE=0 in the environment
-// disables the search and uses NR = 3, 64 sites, no persistence.
+// disables the search and uses NR = 3, 64 sites, no persistence;
+// WILSON_EO_TUNE_CACHE=<file> keeps the tuned shapes across processes.
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <map>
 #include <mutex>
@@ -775,6 +777,87 @@ bool tuning_verbose() {
     return e && e[0] == '1';
 }
 
+// ---- persistent tuning cache ----------------------------------------------
+// WILSON_EO_TUNE_CACHE names a text file that carries tuned shapes across
+// processes: a header line naming the cache version and the GPU
+// architecture, then one line per key
+//   lx ly lz lt fmt nrhs epilogue  nr sites persist bz split  us
+// A file with another header is ignored and rewritten on the next tuning.
+// An entry is used only if its shape is among the current candidates for
+// that key (so a stale or edited file can pick a slower shape, never an
+// invalid launch).  New results are appended, one line per write.
+constexpr int kTuneCacheVersion = 2;
+
+const char* tune_cache_path() {
+    const char* p = getenv("WILSON_EO_TUNE_CACHE");
+    return p && p[0] ? p : nullptr;
+}
+
+std::map<TuneKey, TuneEntry> g_cached;       // entries read from the file
+bool g_cache_loaded = false;
+bool g_cache_header_ok = false;               // the file exists with our header
+
+void cache_header(char* buf, size_t len) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    const char* arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    snprintf(buf, len, "# wilson_eo tuning cache %d %s", kTuneCacheVersion, arch);
+}
+
+// with g_tune_mu held
+void load_cache_locked() {
+    if (g_cache_loaded) return;
+    g_cache_loaded = true;
+    const char* path = tune_cache_path();
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char want[256], line[512];
+    cache_header(want, sizeof want);
+    if (fgets(line, sizeof line, f)) {
+        line[strcspn(line, "\r\n")] = 0;
+        g_cache_header_ok = strcmp(line, want) == 0;
+    }
+    while (g_cache_header_ok && fgets(line, sizeof line, f)) {
+        int v[12];
+        float us = 0.f;
+        if (sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %f", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
+                   &v[6], &v[7], &v[8], &v[9], &v[10], &v[11], &us) != 13)
+            continue;
+        TuneEntry e;
+        e.cfg = {v[7], v[8], v[9], v[10], v[11]};
+        e.us = us;
+        g_cached[TuneKey{v[0], v[1], v[2], v[3], v[4], v[5], v[6]}] = e;
+    }
+    fclose(f);
+}
+
+// with g_tune_mu held
+void append_cache_locked(const TuneKey& k, const TuneEntry& e) {
+    const char* path = tune_cache_path();
+    if (!path) return;
+    FILE* f = fopen(path, g_cache_header_ok ? "a" : "w");
+    if (!f) return;
+    if (!g_cache_header_ok) {
+        char hdr[256];
+        cache_header(hdr, sizeof hdr);
+        fprintf(f, "%s\n", hdr);
+        g_cache_header_ok = true;
+    }
+    fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %.2f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+            std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), e.cfg.nr, e.cfg.s, e.cfg.persist,
+            e.cfg.bz, e.cfg.split, e.us);
+    fclose(f);
+}
+
+bool is_candidate(const HopLaunch& h, const MrhsCfg& c) {
+    for (const MrhsCfg& d : candidates(h))
+        if (d.nr == c.nr && d.s == c.s && d.persist == c.persist && d.bz == c.bz && d.split == c.split) return true;
+    return false;
+}
+
 hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return hipErrorUnknown;
@@ -872,6 +955,16 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
         const uintptr_t y = reinterpret_cast<uintptr_t>(h.y), o = reinterpret_cast<uintptr_t>(h.out);
         if (y < o + fb && o < y + fb) return launch_hop_single(h, s);
     }
+    if (!have && tuning_enabled()) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_cache_locked();
+        auto it = g_cached.find(key);
+        if (it != g_cached.end() && is_candidate(h, it->second.cfg)) {
+            e = it->second;
+            g_tune[key] = e;
+            have = true;
+        }
+    }
     if (!have) {
         if (tuning_enabled()) {
             const hipError_t err = tune(h, s, &e);
@@ -882,6 +975,7 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
         }
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = e;
+        if (tuning_enabled()) append_cache_locked(key, e);
     }
     return run_cfg(h, e.cfg, s);
 }

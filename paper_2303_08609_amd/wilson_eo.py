@@ -1,8 +1,9 @@
 """ctypes binding of libwilson_eo.so (names and arguments as in wilson_eo.h).
 
 Argument marshalling only: every computation runs in the library's HIP
-kernels.  The library is loaded from this package directory; if it is missing
-``load()`` raises instead of falling back to anything else.
+kernels.  The library is loaded from this package directory (or from the
+path in WILSON_EO_LIB); if it is missing ``load()`` raises instead of falling
+back to anything else.
 """
 from __future__ import annotations
 
@@ -120,11 +121,14 @@ class SolverWarning(RuntimeWarning):
     broke down (WEO_BREAKDOWN); the returned x is the last iterate."""
 
 
-def load(path: str = LIB_PATH):
-    """Load libwilson_eo.so and declare its signatures (idempotent)."""
+def load(path: str | None = None):
+    """Load libwilson_eo.so and declare its signatures (idempotent).  The
+    environment variable WILSON_EO_LIB names another build of the library
+    (e.g. the sanitizer build) to load instead of the in-tree one."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("WILSON_EO_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise OSError(f"{path} is not built; run `python -m paper_2303_08609_amd.build`")
     lib = C.CDLL(path)

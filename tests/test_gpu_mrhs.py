@@ -170,3 +170,57 @@ def test_twelve_rhs_32_3x64_sampled(fmt_t):
         assert rel_err(hop[r][sites], want) <= TOL[sp], ("hop", r)
         want = W.apply_m_at_sites(u_or, b_or[r], 0.126, ph, sites)
         assert rel_err(app[r][sites], want) <= TOL[sp], ("apply", r)
+
+
+_CACHE_CHILD = r"""
+import hashlib, json, sys
+import torch
+from paper_2303_08609_amd import inputs
+from paper_2303_08609_amd import wilson_eo as WE
+from paper_2303_08609_amd.ops import Format, Lattice, to_device
+dims = (8, 8, 8, 16)
+lat = Lattice(dims, 0.125, (1, 1, 1, -1))
+fmt = Format("f32", "f32", 18)
+u = lat.pack_gauge(to_device(inputs.gen_gauge(dims, 0.5, 760)), fmt)
+x = lat.pack_spinor(to_device(inputs.gen_spinor_half(dims, 761, nrhs=12)), fmt)
+out = lat.hop(u, x, fmt, 1, nrhs=12)
+torch.cuda.synchronize()
+rep = [json.loads(l) for l in WE.tuning_report().splitlines() if l.strip()]
+print(json.dumps({"report": rep, "sha": hashlib.sha256(out.cpu().numpy().tobytes()).hexdigest()}))
+"""
+
+
+def _cache_child(path):
+    import json
+    import os
+    import subprocess
+    import sys
+    env = dict(os.environ, WILSON_EO_TUNE_CACHE=str(path))
+    env.pop("WEO_TUNE", None)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, "-c", _CACHE_CHILD], env=env, cwd=root, capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 0, p.stderr[-2000:]
+    return json.loads(p.stdout.strip().splitlines()[-1])
+
+
+def test_tuning_cache_across_processes(tmp_path):
+    """WILSON_EO_TUNE_CACHE: a first process tunes the 12-rhs hop and writes
+    the header and one line; a second reads the shape back (same shape and
+    recorded time, nothing appended) and produces the same output bits; a
+    file with a foreign header is rewritten by a fresh tuning."""
+    path = tmp_path / "tune.txt"
+    print("tuning cache: first process", flush=True)
+    a = _cache_child(path)
+    lines = path.read_text().splitlines()
+    assert lines[0].startswith("# wilson_eo tuning cache ") and len(lines) == 2, lines
+    print("tuning cache: second process", flush=True)
+    b = _cache_child(path)
+    assert path.read_text().splitlines() == lines
+    assert b["report"] == a["report"] and b["sha"] == a["sha"]
+    path.write_text("# some other cache\n8 8 8 16 2 12 0 -1 64 0 0 0 1.00\n")
+    print("tuning cache: foreign header", flush=True)
+    c = _cache_child(path)
+    lines = path.read_text().splitlines()
+    assert lines[0].startswith("# wilson_eo tuning cache ") and len(lines) == 2, lines
+    assert c["sha"] == a["sha"] or c["report"] != a["report"]
