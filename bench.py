@@ -384,7 +384,7 @@ def main():
             del ud, xd, tmp
         # twelve right-hand sides through the multi-rhs kernel (tuned shape)
         b12 = torch.from_numpy(inputs.gen_point_noise_sources(DIMS, 406)).cuda()
-        for vs in ("f32/f32/18", "f16/f16/12"):
+        for vs in ("f32/f32/18", "f16/f16/12", "f64/f64/12"):
             f2 = Format(*parse_fmt(vs))
             ud = lat.pack_gauge(u_dev64, f2)
             xd = lat.pack_spinor(b12, f2)

@@ -104,22 +104,29 @@ int weo_selftest(void);
 int weo_format_supported(const weo_format* fmt);
 
 /* Launch shape of hops with nrhs > 1 (used by hop, apply and the solvers).
- * The multi-rhs kernel loads each link once per lane and applies it to nr
- * right-hand sides (the batching the paper's solvers would need for many
- * sources; the paper itself treats one).  nr = 0 (default): an autotuner
- * times every candidate shape on the first call per (lattice, format,
- * nrhs) -- on the caller's stream and buffers, with one stream
- * synchronisation -- and caches the fastest for the process.  nr = 1: one
- * lane per (site, rhs).  nr = -1: one lane per site holding its 8 links in
- * registers while it walks all right-hand sides in turn (FP32/FP16/BF16
- * spinors; FP64 falls back to nr = 1).  nr in {2, 3, 4, 6} (FP64 uses at
- * most 3) with
- * sites per workgroup in {64, 128, 256}, persist in {0, 1}, bz in 0..64 and
- * split in {0, 1} forces that shape.  bz > 0 visits the lattice in strips of
- * bz z-planes, all t per strip (ignored where the lattice or workgroup size
- * does not allow it); split = 1 gives each group of nr rhs its own
- * workgroups and sweep of the lattice.  Returns WEO_ERR_ARG for other values.
- * The setting is process-wide. */
+ * The multi-rhs kernels share each loaded link between right-hand sides
+ * (the batching the paper's solvers would need for many sources; the paper
+ * itself treats one).  nr = 0 (default): an autotuner times every candidate
+ * shape on the first call per (lattice, format, nrhs, epilogue) -- on the
+ * caller's stream and buffers, with one stream synchronisation -- and caches
+ * the fastest for the process.  nr = 1: one lane per (site, rhs).
+ * nr in {2, 3, 4, 6} (FP64 uses at most 3): a lane applies each link it
+ * loads to nr right-hand sides.  nr = -1 / -3: one lane per site holding its
+ * 8 links in registers while it walks all right-hand sides (neighbour ring
+ * depth 1 / 3; FP32, FP16 and BF16 spinors, FP64 falls back to nr = 1);
+ * nr = -2 / -4: the same with FP16 arithmetic on packed pairs (FP16
+ * spinors and links; other formats fall back to -1 / -3).  For these,
+ * sites per workgroup is 64, 128 or 256.  nr = -5: the 64 sites' links
+ * staged in LDS and shared by `sites` wavefronts (2, 3, 4, 6, 8 or 12;
+ * clamped to 4 for FP64 and 8 for FP16/BF16 spinors), each walking every
+ * sites-th right-hand side (all formats); here split = 0 sweeps the lattice
+ * once for all right-hand sides, split = f in 1..16 once per f of them
+ * (the links staged again per sweep).  persist in {0, 1}, bz in 0..64 and
+ * split in {0, 1} (for nr > 1) complete the shape.  bz > 0 visits the lattice in strips of bz z-planes, all t per
+ * strip (ignored where the lattice or workgroup size does not allow it);
+ * split = 1 gives each group of nr rhs its own workgroups and sweep of the
+ * lattice.  Returns WEO_ERR_ARG for other values.  The setting is
+ * process-wide. */
 int weo_set_mrhs_shape(int nr, int sites, int persist, int bz, int split);
 
 /* The autotuner's cached choices as JSON lines in buf (NUL-terminated,

@@ -38,16 +38,7 @@ __global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_ho
             hop_mu<SP, LP, L12, DAG, CPH, 2>(P, in, nb, ih, acc);
             hop_mu<SP, LP, L12, DAG, CPH, 3>(P, in, nb, ih, acc);
         }
-        if constexpr (AXPY) {
-            C yv[12];
-            load_rec<SP, 12>(P.y + (size_t)rhs * P.spinor_bytes, P.g.vh, ih, yv);
-            const R a = (R)P.alpha;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                acc[k].x = fma(a, acc[k].x, yv[k].x);
-                acc[k].y = fma(a, acc[k].y, yv[k].y);
-            }
-        }
+        if constexpr (AXPY) hop_addends<SP>(P, (size_t)rhs, ih, acc);
         store_rec<SP, 12, C, hop_nt_store<SP>()>(out, P.g.vh, ih, acc);
         if constexpr (NORM) {
             // norm of the value as stored (rounded to the storage precision)
@@ -133,6 +124,8 @@ hipError_t launch_hop_single(const HopLaunch& h, hipStream_t s) {
     P.in = static_cast<const uint8_t*>(h.in);
     P.out = static_cast<uint8_t*>(h.out);
     P.y = static_cast<const uint8_t*>(h.y);
+    P.z = static_cast<const uint8_t*>(h.z);
+    P.cy = h.cy;
     P.alpha = h.alpha;
     P.partial = h.partial;
     P.spinor_bytes = spinor_field_bytes(h.g, h.fmt);

@@ -102,12 +102,38 @@ struct HopParams {
     const uint8_t* in;      // nrhs fields of parity 1 - out_par
     uint8_t* out;           // nrhs fields of parity out_par
     const uint8_t* y;       // axpy addend (parity out_par) or null
+    const uint8_t* z;       // second addend (with y only) or null
+    double cy;              // coefficient of y
     double alpha;
     double* partial;
     size_t spinor_bytes;    // bytes of one packed spinor field
     size_t link_block;      // bytes of one (mu, parity) link block
     Sched sched;            // workgroup -> sites order
 };
+
+// Epilogue of a hop with addends: acc = alpha acc + cy y (+ z) for rhs r at
+// site ih (cy = 1 rounds exactly as a plain axpy).
+template <int SP, class C>
+__device__ __forceinline__ void hop_addends(const HopParams& P, size_t r, uint32_t ih, C* acc) {
+    using R = decltype(C().x);
+    C yv[12];
+    load_rec<SP, 12>(P.y + r * P.spinor_bytes, P.g.vh, ih, yv);
+    const R a = (R)P.alpha, c = (R)P.cy;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        acc[k].x = fma(a, acc[k].x, c * yv[k].x);
+        acc[k].y = fma(a, acc[k].y, c * yv[k].y);
+    }
+    if (P.z) {
+        C zv[12];
+        load_rec<SP, 12>(P.z + r * P.spinor_bytes, P.g.vh, ih, zv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            acc[k].x += zv[k].x;
+            acc[k].y += zv[k].y;
+        }
+    }
+}
 
 // Link U as 9 complex numbers (row-major); a 12-real record is completed with
 // row 2 = conj(row0 x row1), exact for det U = 1.

@@ -36,10 +36,18 @@
 
 namespace weo {
 
+// The LDS-staged form (k_hop_lw) in MrhsCfg::nr (MrhsCfg::s then holds the
+// wavefronts per workgroup).
+constexpr int kNrLw = -5;
+#ifndef LW_CROSS
+#define LW_CROSS (SP != P_F64)
+#endif
+
 struct MrhsParams {
     HopParams h;
     int nrhs;
     uint32_t nblk;      // site blocks of blockDim.x sites
+    int rhs_per_row;    // LDS-staged form: right-hand sides per grid row
 };
 
 // Raw words of one neighbour: its link and the NR spinor records.
@@ -162,16 +170,7 @@ __global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
             for (int q = 0; q < NR; ++q) {
                 const int r = r0 + q;
                 if (r < M.nrhs) {
-                    if (P.y) {
-                        C yv[12];
-                        load_rec<SP, 12>(P.y + (size_t)r * P.spinor_bytes, P.g.vh, ih, yv);
-                        const R a = (R)P.alpha;
-#pragma unroll
-                        for (int k = 0; k < 12; ++k) {
-                            acc[q][k].x = fma(a, acc[q][k].x, yv[k].x);
-                            acc[q][k].y = fma(a, acc[q][k].y, yv[k].y);
-                        }
-                    }
+                    if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc[q]);
                     uint8_t* out = P.out + (size_t)r * P.spinor_bytes;
                     store_rec<SP, 12, C, hop_nt_store<SP>()>(out, P.g.vh, ih, acc[q]);
                     if (P.partial) {
@@ -304,16 +303,7 @@ __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) acc[k] = czero<C>();
                 lr_step<SP, LP, L12, DAG, CPH, D, 0>(P, in, in_next, nb, lk, ring, acc);
-                if (P.y) {
-                    C yv[12];
-                    load_rec<SP, 12>(P.y + (size_t)r * P.spinor_bytes, n, ih, yv);
-                    const R a = (R)P.alpha;
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        acc[k].x = fma(a, acc[k].x, yv[k].x);
-                        acc[k].y = fma(a, acc[k].y, yv[k].y);
-                    }
-                }
+                if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc);
                 store_rec<SP, 12>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
                 if (P.partial) {
                     C st[12];
@@ -332,6 +322,176 @@ __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
                 const double t = wave_sum64(nrm);
                 const uint32_t chunk = (base + (threadIdx.x & ~63u)) >> 6;
                 if ((threadIdx.x & 63) == 0 && chunk < nchunk) P.partial[(size_t)r * nchunk + chunk] = t;
+            }
+        }
+    }
+}
+
+// ---- links staged in LDS, right-hand sides across wavefronts --------------------
+// A workgroup of W wavefronts owns 64 output sites.  The wavefronts first
+// copy the raw words of the 64 sites' 8 links from memory into LDS (each
+// wavefront some of the directions), then each walks its own right-hand
+// sides (w, w + W, ...) with the single-rhs pipeline, taking the links from
+// LDS.  Every link is read from memory once per launch, as in the
+// link-resident form, but the links occupy LDS shared by W wavefronts
+// instead of registers of each lane, so the register footprint is the
+// single-rhs kernel's: this is the form that exists for FP64 (whose 8 links
+// do not fit a lane's registers next to its pipeline), and a candidate for
+// the other formats.  LDS holds the links as [direction][16-byte slot][site]
+// (a tail of 4 or 8 bytes takes a whole slot), so the 64 lanes of a read
+// touch 1 KiB of consecutive words.
+template <int SP, int LP, bool L12> struct LwShape {
+    using LRaw = RawRec<LP, L12 ? 6 : 9, hop_nt<SP>()>;
+    static constexpr int NC = Rec<LP, L12 ? 6 : 9>::NFULL;
+    static constexpr int TB = Rec<LP, L12 ? 6 : 9>::TAILB;
+    static constexpr int NS = NC + (TB ? 1 : 0);     // 16-byte slots per link
+    static constexpr int LDS_U4 = 8 * NS * 64;
+};
+
+template <int SP, int LP, bool L12>
+__device__ __forceinline__ void lw_put(uint4* lds, int k, uint32_t lane,
+                                       const typename LwShape<SP, LP, L12>::LRaw& r) {
+    using Sh = LwShape<SP, LP, L12>;
+#pragma unroll
+    for (int p = 0; p < Sh::NC; ++p) lds[(k * Sh::NS + p) * 64 + lane] = r.w[p];
+    if constexpr (Sh::TB == 8) lds[(k * Sh::NS + Sh::NC) * 64 + lane] = make_uint4(r.t8.x, r.t8.y, 0u, 0u);
+    if constexpr (Sh::TB == 4) lds[(k * Sh::NS + Sh::NC) * 64 + lane] = make_uint4(r.t4, 0u, 0u, 0u);
+}
+
+template <int SP, int LP, bool L12>
+__device__ __forceinline__ void lw_get(const uint4* lds, int k, uint32_t lane,
+                                       typename LwShape<SP, LP, L12>::LRaw& r) {
+    using Sh = LwShape<SP, LP, L12>;
+#pragma unroll
+    for (int p = 0; p < Sh::NC; ++p) r.w[p] = lds[(k * Sh::NS + p) * 64 + lane];
+    if constexpr (Sh::TB == 8) {
+        const uint4 v = lds[(k * Sh::NS + Sh::NC) * 64 + lane];
+        r.t8 = make_uint2(v.x, v.y);
+    }
+    if constexpr (Sh::TB == 4) r.t4 = lds[(k * Sh::NS + Sh::NC) * 64 + lane].x;
+}
+
+template <int SP> constexpr int lw_depth() { return 1; }
+// Most wavefronts per workgroup: FP64 keeps the single-rhs register budget
+// (256 VGPRs, as the FP64 single-rhs hop), so at most 4; FP32 fits 3 waves
+// per SIMD at up to 12; FP16 / BF16 at up to 8 (12 spills a little).
+template <int SP> constexpr int lw_maxw() { return SP == P_F64 ? 4 : (SP == P_F32 ? 12 : 8); }
+// Prefetch of the next right-hand side's first records across the epilogue
+// (off for FP64: its records held through the epilogue spill).
+template <int SP> constexpr bool lw_cross() { return LW_CROSS; }
+
+template <int SP, int LP, bool L12> struct LwSlot {
+    RawRec<SP, 12> sp;
+    typename LwShape<SP, LP, L12>::LRaw ln;
+};
+
+// Ring of D+1 slots as in the link-resident form: the neighbour record and
+// the link words of direction K + D are fetched while direction K is
+// computed; the last D directions of one right-hand side fetch the first
+// records of the next.
+template <int SP, int LP, bool L12, bool DAG, bool CPH, int D, int K, class C>
+__device__ __forceinline__ void lw_step(const HopParams& P, const uint4* lds, uint32_t lane, const uint8_t* in,
+                                        const uint8_t* in_next, const Nbr& nb, LwSlot<SP, LP, L12> (&ring)[D + 1],
+                                        C* acc) {
+    constexpr int KN = (K + D) & 7;
+    if constexpr (K + D < 8 || lw_cross<SP>()) {
+        LwSlot<SP, LP, L12>& nx = ring[(K + D) % (D + 1)];
+        nx.sp.load(K + D < 8 ? in : in_next, P.g.vh, nb.i[KN]);
+        lw_get<SP, LP, L12>(lds, KN, lane, nx.ln);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    lr_consume<SP, LP, L12, DAG, CPH, K>(P, nb, ring[K % (D + 1)].ln, ring[K % (D + 1)].sp, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (K + 1 < 8) lw_step<SP, LP, L12, DAG, CPH, D, K + 1>(P, lds, lane, in, in_next, nb, ring, acc);
+}
+
+
+template <int SP, int LP, bool L12, bool DAG, bool CPH>
+__global__ void __launch_bounds__(64 * lw_maxw<SP>()) k_hop_lw(const MrhsParams M) {
+    using R = typename Arith<SP>::R;
+    using C = cx<R>;
+    using Sh = LwShape<SP, LP, L12>;
+    constexpr int D = lw_depth<SP>();
+    __shared__ uint4 lds[Sh::LDS_U4];
+    const HopParams& P = M.h;
+    const uint32_t n = P.g.vh;
+    const uint32_t nchunk = (n + 63) >> 6;
+    const uint32_t lane = threadIdx.x;                    // blockDim.x == 64
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int W = (int)blockDim.y;
+    // this grid row's right-hand sides [r0, r1): rows are separate sweeps
+    const int r0 = (int)blockIdx.y * M.rhs_per_row;
+    const int r1 = r0 + M.rhs_per_row < M.nrhs ? r0 + M.rhs_per_row : M.nrhs;
+    for (uint32_t b = blockIdx.x; b < M.nblk; b += gridDim.x) {
+        const uint32_t blk = xcd_block(b, M.nblk, P.remap);
+        const uint32_t base = block_first_site(P.sched, P.g, blk, 64);
+        const uint32_t ih = base + lane;
+        const bool valid = ih < n;
+        Nbr nb;
+        if (valid) nb = neighbours(P.g, decode(P.g, ih, P.out_par));
+        __syncthreads();                                  // the previous block's links are consumed
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (k % W != wv) continue;                // wave-uniform
+                const int mu = k >> 1;
+                const bool fwd = (k & 1) == 0;
+                typename Sh::LRaw r;
+                r.load(P.u + (size_t)(2 * mu + (fwd ? P.out_par : 1 - P.out_par)) * P.link_block, n,
+                       fwd ? ih : nb.i[k]);
+                lw_put<SP, LP, L12>(lds, k, lane, r);
+            }
+        }
+        __syncthreads();
+        LwSlot<SP, LP, L12> ring[D + 1];
+        if (lw_cross<SP>() && valid && r0 + wv < r1) {
+            const uint8_t* in0 = P.in + (size_t)(r0 + wv) * P.spinor_bytes;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                ring[k].sp.load(in0, n, nb.i[k]);
+                lw_get<SP, LP, L12>(lds, k, lane, ring[k].ln);
+            }
+        }
+        for (int r = r0 + wv; r < r1; r += W) {
+            double nrm = 0.0;
+            if (valid) {
+                const uint8_t* in = P.in + (size_t)r * P.spinor_bytes;
+                if constexpr (!lw_cross<SP>()) {
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        ring[k].sp.load(in, n, nb.i[k]);
+                        lw_get<SP, LP, L12>(lds, k, lane, ring[k].ln);
+                    }
+                }
+                const uint8_t* in_next = r + W < r1 ? in + (size_t)W * P.spinor_bytes : in;
+                // an opaque copy of the lane index per right-hand side: the LDS
+                // link words are invariant in this loop, and without it the
+                // compiler hoists all 8 links' reads out of it into registers
+                uint32_t lo = lane;
+                asm volatile("" : "+v"(lo));
+                C acc[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = czero<C>();
+                lw_step<SP, LP, L12, DAG, CPH, D, 0>(P, lds, lo, in, in_next, nb, ring, acc);
+                if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc);
+                store_rec<SP, 12, C, hop_nt_store<SP>()>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
+                if (P.partial) {
+                    C st[12];
+                    if constexpr (SP == P_F64 || SP == P_F32) {
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) st[k] = acc[k];
+                    } else {
+                        round_rec<SP, 12>(acc, st);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        nrm += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
+                }
+            }
+            if (P.partial) {
+                const double t = wave_sum64(nrm);
+                const uint32_t chunk = base >> 6;
+                if (lane == 0 && chunk < nchunk) P.partial[(size_t)r * nchunk + chunk] = t;
             }
         }
     }
@@ -546,16 +706,7 @@ __global__ void __launch_bounds__(256) k_hop_lr16(const MrhsParams M) {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) acc[k] = make_float2(0.f, 0.f);
                 h16_step<DAG, D, 0>(P, in, in_next, nb, lk, ring, acc);
-                if (P.y) {
-                    float2 yv[12];
-                    load_rec<P_F16, 12>(P.y + (size_t)r * P.spinor_bytes, n, ih, yv);
-                    const float a = (float)P.alpha;
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        acc[k].x = fmaf(a, acc[k].x, yv[k].x);
-                        acc[k].y = fmaf(a, acc[k].y, yv[k].y);
-                    }
-                }
+                if (P.y) hop_addends<P_F16>(P, (size_t)r, ih, acc);
                 store_rec<P_F16, 12>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
                 if (P.partial) {
                     float2 st[12];
@@ -585,6 +736,8 @@ static HopParams hop_params(const HopLaunch& h) {
     P.in = static_cast<const uint8_t*>(h.in);
     P.out = static_cast<uint8_t*>(h.out);
     P.y = static_cast<const uint8_t*>(h.y);
+    P.z = static_cast<const uint8_t*>(h.z);
+    P.cy = h.cy;
     P.alpha = h.alpha;
     P.partial = h.partial;
     P.spinor_bytes = spinor_field_bytes(h.g, h.fmt);
@@ -677,9 +830,66 @@ static hipError_t launch_hop_lr(const HopLaunch& h, const MrhsParams& M, int dep
 
 bool lr_supported(int fmt) { return fmt_info(fmt).spinor_prec != P_F64; }
 
+template <int SP, int LP, bool L12>
+static hipError_t lw_fmt(const HopLaunch& h, const MrhsParams& M, dim3 grid, dim3 block, hipStream_t s) {
+    bool cph = false;
+    for (int m = 0; m < 4; ++m) cph = cph || h.phase[m][1] != 0.0;
+#define WEO_LW(DG, CP) hipLaunchKernelGGL((k_hop_lw<SP, LP, L12, DG, CP>), grid, block, 0, s, M)
+    if (h.dagger) { if (cph) WEO_LW(true, true); else WEO_LW(true, false); }
+    else { if (cph) WEO_LW(false, true); else WEO_LW(false, false); }
+#undef WEO_LW
+    return hipGetLastError();
+}
+
+static int lw_max_waves(int fmt) {
+    switch (fmt_info(fmt).spinor_prec) {
+        case P_F64: return lw_maxw<P_F64>();
+        case P_F32: return lw_maxw<P_F32>();
+        default: return lw_maxw<P_F16>();
+    }
+}
+
+// LDS-staged form: W wavefronts of 64 sites per workgroup
+static hipError_t launch_hop_lw(const HopLaunch& h, const MrhsParams& M, int W, dim3 grid, hipStream_t s) {
+    if (W > lw_max_waves(h.fmt)) return hipErrorInvalidValue;
+    const dim3 block(64, (unsigned)W);
+    switch (h.fmt) {
+        case FMT_D_D_18: return lw_fmt<P_F64, P_F64, false>(h, M, grid, block, s);
+        case FMT_D_D_12: return lw_fmt<P_F64, P_F64, true>(h, M, grid, block, s);
+        case FMT_S_S_18: return lw_fmt<P_F32, P_F32, false>(h, M, grid, block, s);
+        case FMT_S_S_12: return lw_fmt<P_F32, P_F32, true>(h, M, grid, block, s);
+        case FMT_H_H_18: return lw_fmt<P_F16, P_F16, false>(h, M, grid, block, s);
+        case FMT_H_H_12: return lw_fmt<P_F16, P_F16, true>(h, M, grid, block, s);
+        case FMT_B_H_18: return lw_fmt<P_BF16, P_F16, false>(h, M, grid, block, s);
+        case FMT_B_H_12: return lw_fmt<P_BF16, P_F16, true>(h, M, grid, block, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool lw_waves_ok(int w) { return w == 2 || w == 3 || w == 4 || w == 6 || w == 8 || w == 12; }
+
 hipError_t launch_hop_mrhs(const HopLaunch& h, const MrhsCfg& c, hipStream_t s) {
     MrhsParams M;
     M.h = hop_params(h);
+    M.rhs_per_row = h.nrhs;
+    if (c.nr == kNrLw) {
+        // LDS-staged: 64 sites per workgroup, c.s wavefronts
+        if (!lw_waves_ok(c.s)) return hipErrorInvalidValue;
+        M.h.sched = make_sched(h.g, c.bz, 64u);
+        M.nrhs = h.nrhs;
+        M.nblk = (h.g.vh + 63u) / 64u;
+        // c.split = right-hand sides per sweep (0: all in one); each sweep
+        // is a grid row and stages the links again
+        M.rhs_per_row = c.split > 0 && c.split < h.nrhs ? c.split : h.nrhs;
+        const unsigned rows = (unsigned)((h.nrhs + M.rhs_per_row - 1) / M.rhs_per_row);
+        uint32_t nwg = M.nblk;
+        if (c.persist) {
+            const uint32_t cap = 8u * 256u;
+            if (nwg > cap) nwg = cap;
+            nwg = ((nwg + 7u) / 8u) * 8u;
+        }
+        return launch_hop_lw(h, M, c.s, dim3(nwg, rows), s);
+    }
     M.h.sched = make_sched(h.g, c.bz, (uint32_t)c.s);
     if (c.nr < 0) {
         // link-resident: one lane per site, all rhs in turn; -nr is the ring depth
@@ -748,6 +958,17 @@ std::vector<MrhsCfg> candidates(const HopLaunch& h) {
                     if (lr16_supported(h.fmt))
                         for (int nr : {-2, -4}) v.push_back({nr, s, persist, bz, 0});
                 }
+    for (int w : {2, 3, 4, 6, 8, 12}) {
+        if (w > h.nrhs || w > lw_max_waves(h.fmt)) continue;
+        for (int persist : {0, 1})
+            for (int bz : {0, 2, 4, 8}) {
+                if (bz && make_sched(h.g, bz, 64u).bz != bz) continue;
+                for (int f : {0, 6}) {                // right-hand sides per sweep (0: all)
+                    if (f && (f >= h.nrhs || f < w)) continue;
+                    v.push_back({kNrLw, w, persist, bz, f});
+                }
+            }
+    }
     const int nrs[] = {2, 3, 4, 6};
     for (int nr : nrs) {
         if (nr > h.nrhs || (wide && nr > 3)) continue;
@@ -896,6 +1117,14 @@ int set_mrhs_shape(int nr, int sites, int persist, int bz, int split) {
         g_forced = {nr, 0, 0, 0, 0};
         return 0;
     }
+    if (nr == kNrLw) {
+        if (!lw_waves_ok(sites) || (persist != 0 && persist != 1) || bz < 0 || bz > 64 || split < 0 ||
+            split > 16)       // 16: the most right-hand sides of a launch
+            return -1;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_forced = {nr, sites, persist, bz, split};
+        return 0;
+    }
     if (nr < -4) return -1;
     if (split != 0 && split != 1) return -1;
     if (nr < 0) {
@@ -923,6 +1152,11 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
         forced = g_forced;
     }
     if (forced.nr == 1) return launch_hop_single(h, s);
+    if (forced.nr == kNrLw) {
+        MrhsCfg c = forced;
+        if (c.s > lw_max_waves(h.fmt)) c.s = lw_max_waves(h.fmt);      // the format's most wavefronts
+        return launch_hop_mrhs(h, c, s);
+    }
     if (forced.nr < 0) {
         if (!lr_supported(h.fmt)) return launch_hop_single(h, s);
         if ((forced.nr == -2 || forced.nr == -4) && !lr16_supported(h.fmt)) {
@@ -939,7 +1173,7 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
         if (c.nr > h.nrhs) c.nr = h.nrhs;
         return c.nr <= 1 ? launch_hop_single(h, s) : launch_hop_mrhs(h, c, s);
     }
-    const int epi = (h.y != nullptr ? 1 : 0) + (h.partial != nullptr ? 2 : 0);
+    const int epi = (h.y != nullptr ? 1 : 0) + (h.partial != nullptr ? 2 : 0) + (h.z != nullptr ? 4 : 0);
     const TuneKey key{h.g.lx, h.g.ly, h.g.lz, h.g.lt, h.fmt, h.nrhs, epi};
     TuneEntry e;
     bool have = false;

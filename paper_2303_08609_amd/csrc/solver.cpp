@@ -46,6 +46,8 @@
 #include <cmath>
 #include <complex>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -61,6 +63,12 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb);
 void phases_of(const weo_lattice* lat, double ph[4][2]);
 
 namespace {
+
+// WILSON_EO_LOG=1: one line per defect-correction step on stderr.
+bool solver_log() {
+    const char* e = getenv("WILSON_EO_LOG");
+    return e && e[0] == '1';
+}
 
 #define HIPCHK(expr)                                  \
     do {                                              \
@@ -265,6 +273,38 @@ hipError_t apply_a(Ctx& c, int fmt, const void* u, int dagger, const void* in, v
                    int nrhs, double* partial) {
     if (c.full) return apply_dw(c, fmt, u, dagger, in, out, nrhs, partial);
     return apply_m(c, fmt, u, dagger, in, out, tmp, nrhs, partial);
+}
+
+// r = b - M x in two hops: tmp = H_oe x, then r = kappa^2 H_eo tmp - x + b
+// in the second hop's epilogue (no M x field written and read back);
+// partial = ||r||^2 per 64 sites.  Wilson M only (no site blocks).
+hipError_t resid_m(Ctx& c, int fmt, const void* u, const void* x, const void* b, void* r, void* tmp, int nrhs,
+                   double* partial) {
+    HopLaunch h;
+    h.g = c.g;
+    h.fmt = fmt;
+    h.dagger = 0;
+    std::memcpy(h.phase, c.ph, sizeof(h.phase));
+    h.u = u;
+    h.nrhs = nrhs;
+    h.out_par = 1;
+    h.in = x;
+    h.out = tmp;
+    h.y = nullptr;
+    h.alpha = 0.0;
+    h.partial = nullptr;
+    hipError_t e = launch_hop(h, c.st);
+    if (e != hipSuccess) return e;
+    h.out_par = 0;
+    h.in = tmp;
+    h.out = r;
+    h.y = x;
+    h.cy = -1.0;
+    h.z = b;
+    h.alpha = c.lat->kappa * c.lat->kappa;
+    h.partial = partial;
+    ++c.applies;
+    return launch_hop(h, c.st);
 }
 
 // out = A x for the solver operator (M, or M^dag M through mid); partial = ||out||^2
@@ -1098,6 +1138,12 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
         if (lr.breakdown && status != WEO_OK) status = WEO_BREAKDOWN;
     } else {
         // FP64 defect correction around inner solves in the inner format.
+        // Right-hand sides that meet the tolerance drop out: from then on the
+        // FP64 residuals and the inner solves run on the live ones only,
+        // compacted to the front of the work fields (live[j] is the rhs in
+        // compact slot j), so a last step for a few stragglers costs a few
+        // fields, not n.  (M^dag M keeps all n: its residual needs a second
+        // FP64 intermediate field.)
         const double target = 12.0 * (double)gb.vh;    // unit RMS per complex component
         if (!p->x0_given) HIPCHK(launch_zero(x, fb, c.st));
         int inner_iters = 0, k = 0;
@@ -1105,48 +1151,104 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
         std::vector<double> rel(n), bb0(n);
         HIPCHK(hipMemcpyAsync(bb0.data(), w.sc.bb, n * sizeof(double), hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipStreamSynchronize(c.st));
+        const size_t f1 = spinor_field_bytes(gb, id), fa1 = spinor_field_bytes(gb, kAccF32);
+        const bool can_compact = p->op != WEO_OP_MDAGM;
+        // the Wilson M residual in one fused pass (site blocks and D_W take
+        // the operator, then b - A x)
+        const bool fused_resid = p->op == WEO_OP_M && !p->clover;
+        auto at = [](const void* base, size_t bytes, int j) {
+            return static_cast<uint8_t*>(const_cast<void*>(base)) + (size_t)j * bytes;
+        };
+        std::vector<int> cur(n);            // rhs of compact slot j (slots of r64, sc_in, sc_out)
+        for (int r = 0; r < n; ++r) cur[r] = r;
         for (;;) {
-            // r64 = b - A x; rr = ||r64||^2.  From a zero start the residual is
-            // b itself, whose norm partials are still in pa.
+            const int m = (int)cur.size();
+            const bool dense = m == n;      // slot j holds rhs j
+            // r64 = b - A x, rr = ||r64||^2 for the rhs in cur.  From a zero
+            // start the residual is b itself, whose norm partials are still in pa.
             const bool from_zero = k == 0 && !p->x0_given;
             const void* r64 = from_zero ? b : w.r64;
-            if (!from_zero) {
+            int nba = (int)nbb;             // partials per rhs in pa
+            if (!from_zero && dense && fused_resid) {
+                HIPCHK(resid_m(c, id, u, x, b, w.r64, w.tmp64, n, w.pa));
+                nba = (int)c.nb_apply;
+            } else if (!from_zero && dense) {
                 HIPCHK(apply_op(c, p->op, id, u, x, w.t64, w.r64, w.tmp64, n, nullptr));
                 HIPCHK(launch_axpby(gb, id, n, 1.0, b, -1.0, w.t64, w.r64, w.pa, c.st));
+            } else if (!from_zero) {
+                // the live x gathered into r64 (free until the axpby below)
+                for (int j = 0; j < m; ++j)
+                    HIPCHK(hipMemcpyAsync(at(w.r64, f1, j), at(x, f1, cur[j]), f1, hipMemcpyDeviceToDevice, c.st));
+                HIPCHK(apply_op(c, p->op, id, u, w.r64, w.t64, nullptr, w.tmp64, m, nullptr));
+                for (int j = 0; j < m; ++j)
+                    HIPCHK(launch_axpby(gb, id, 1, 1.0, at(b, f1, cur[j]), -1.0, at(w.t64, f1, j), at(w.r64, f1, j),
+                                        w.pa + (size_t)j * nbb, c.st));
             }
-            ScalarArgsHost sa = sargs(w.sc, n);
-            sa.pa = w.pa; sa.nba = (int)nbb; sa.target = target;
+            ScalarArgsHost sa = sargs(w.sc, m);
+            sa.pa = w.pa; sa.nba = nba; sa.target = target;
             HIPCHK(launch_scalars(SCAL_SCALE, sa, c.st));
-            std::vector<double> rr(n), bb(n);
-            HIPCHK(hipMemcpyAsync(rr.data(), w.sc.nrm, n * sizeof(double), hipMemcpyDeviceToHost, c.st));
-            HIPCHK(hipMemcpyAsync(bb.data(), w.sc.bb, n * sizeof(double), hipMemcpyDeviceToHost, c.st));
+            std::vector<double> rr(m);
+            HIPCHK(hipMemcpyAsync(rr.data(), w.sc.nrm, m * sizeof(double), hipMemcpyDeviceToHost, c.st));
             HIPCHK(hipStreamSynchronize(c.st));
-            int nlive = 0;
-            for (int r = 0; r < n; ++r) {
-                rel[r] = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : std::sqrt(rr[r]);
-                live[r] = !(rel[r] <= p->tol);
-                nlive += live[r];
+            std::vector<int> keep;          // compact slots still live
+            double worst = 0.0;
+            for (int j = 0; j < m; ++j) {
+                const int r = cur[j];
+                rel[r] = bb0[r] > 0 ? std::sqrt(rr[j] / bb0[r]) : std::sqrt(rr[j]);
+                if (!(rel[r] <= p->tol)) keep.push_back(j);
             }
+            for (int r = 0; r < n; ++r) worst = std::fmax(worst, rel[r]);
+            const int nlive = (int)keep.size();
+            if (solver_log())
+                fprintf(stderr, "[wilson_eo] outer %d: %d of %d rhs live, worst residual %.3e, inner iterations %d\n",
+                        k, nlive, n, worst, inner_iters);
             if (!nlive || k >= p->max_outer || inner_iters >= p->maxiter || breakdown) break;
-            // inner right-hand side: r64 scaled to unit RMS, in FP32; x_acc = 0
-            HIPCHK(convert_fields(c, id, r64, kAccF32, w.s_acc, n, w.sc.sc_in, 0));
-            HIPCHK(launch_zero(w.x_acc, (size_t)n * spinor_field_bytes(gb, kAccF32), c.st));
+            // without compaction every rhs stays in its slot (converged ones
+            // masked off inside the inner solve)
+            std::vector<int> slots = keep;
+            if (!can_compact) {
+                slots.resize(n);
+                for (int j = 0; j < n; ++j) slots[j] = j;
+            }
+            const int mi = (int)slots.size();
+            bool ident = mi == m;
+            for (int j = 0; j < mi && ident; ++j) ident = slots[j] == j;
+            // inner right-hand sides: the slots' r64 scaled to unit RMS, in
+            // FP32, at the front of s_acc; x_acc = 0
+            if (ident) {
+                HIPCHK(convert_fields(c, id, r64, kAccF32, w.s_acc, mi, w.sc.sc_in, 0));
+            } else {
+                for (int j = 0; j < mi; ++j)
+                    HIPCHK(convert_fields(c, id, at(r64, f1, slots[j]), kAccF32, at(w.s_acc, fa1, j), 1,
+                                          w.sc.sc_in + slots[j], 0));
+            }
+            HIPCHK(launch_zero(w.x_acc, (size_t)mi * fa1, c.st));
             // the inner stopping test compares with ||rhs||^2 = target
-            std::vector<double> tg(n, target);
-            HIPCHK(hipMemcpyAsync(w.sc.bb, tg.data(), n * sizeof(double), hipMemcpyHostToDevice, c.st));
-            if ((rc = set_mask(c, w, live)) != WEO_OK) return rc;
+            std::vector<double> tg(mi, target);
+            HIPCHK(hipMemcpyAsync(w.sc.bb, tg.data(), mi * sizeof(double), hipMemcpyHostToDevice, c.st));
+            std::vector<int> mask(mi, 1);
+            if (!can_compact)
+                for (int j = 0; j < mi; ++j) mask[j] = !(rel[cur[j]] <= p->tol);
+            if ((rc = set_mask(c, w, mask)) != WEO_OK) return rc;
             LevelResult lr;
             c.clv = p->clover_inner;
-            rc = run_method(c, w, p->method, p->op, inner, kAccF32, u_inner, w.x_acc, n, p->inner_tol,
+            rc = run_method(c, w, p->method, p->op, inner, kAccF32, u_inner, w.x_acc, mi, p->inner_tol,
                             p->maxiter - inner_iters, p->check_every, &lr);
             c.clv = p->clover;
             if (rc != WEO_OK) return rc;
             inner_iters += lr.iters;
             breakdown = breakdown || lr.breakdown;
-            // x += x_acc * sc_out (only live rhs changed: x_acc = 0 elsewhere)
-            HIPCHK(convert_fields(c, kAccF32, w.x_acc, id, x, n, w.sc.sc_out, 1));
-            // restore ||b||^2 (bb0 outlives the copy: the next look synchronises)
-            HIPCHK(hipMemcpyAsync(w.sc.bb, bb0.data(), n * sizeof(double), hipMemcpyHostToDevice, c.st));
+            // x += x_acc * sc_out (masked rhs have x_acc = 0)
+            std::vector<int> next(mi);
+            for (int j = 0; j < mi; ++j) next[j] = cur[slots[j]];
+            if (ident && dense) {
+                HIPCHK(convert_fields(c, kAccF32, w.x_acc, id, x, n, w.sc.sc_out, 1));
+            } else {
+                for (int j = 0; j < mi; ++j)
+                    HIPCHK(convert_fields(c, kAccF32, at(w.x_acc, fa1, j), id, at(x, f1, next[j]), 1,
+                                          w.sc.sc_out + slots[j], 1));
+            }
+            cur.swap(next);
             ++k;
         }
         info->iters = inner_iters;

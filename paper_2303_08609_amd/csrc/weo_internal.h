@@ -43,6 +43,10 @@ struct HopLaunch {
     double alpha;
     double* partial;      // [nrhs][hop_partials()] or nullptr: one per 64 sites
     int nrhs;
+    // epilogue out = alpha hop + cy y + z (z only with y): cy = 1, z = null is
+    // the axpy of M; cy = -1 with z = b gives the residual b - M x in one pass
+    const void* z = nullptr;
+    double cy = 1.0;
 };
 
 struct TuneCfg {

@@ -95,6 +95,74 @@ def test_fp16_pair_form_matches_oracle(dims, fmt_t, bc):
             assert rel_err(got[r], want) <= TOL[sp], (shape, "axpy", r)
 
 
+LDS_SHAPES = [(-5, w, p, bz, f) for w in (2, 3, 4, 6, 8, 12) for p in (0, 1) for bz in (0, 2) for f in (0, 3)] + \
+    [(-5, 4, 0, 0, 1), (-5, 2, 1, 2, 4), (-5, 3, 0, 0, 5)]
+ALL_FORMATS = [("f64", "f64", 18), ("f64", "f64", 12), ("f32", "f32", 18), ("f32", "f32", 12),
+               ("f16", "f16", 18), ("f16", "f16", 12), ("bf16", "f16", 18), ("bf16", "f16", 12)]
+
+
+@pytest.mark.parametrize("fmt_t", ALL_FORMATS, ids=lambda f: f"{f[0]}-{f[1]}-{f[2]}")
+@pytest.mark.parametrize("dims", [(6, 4, 4, 10), (16, 8, 4, 6)], ids=["ragged", "strips"])
+def test_lds_form_matches_oracle(dims, fmt_t):
+    """The hop with the 64 sites' links staged in LDS and the right-hand
+    sides spread over the workgroup's wavefronts: every wavefront count
+    (more than the format allows is clamped to its most), persistence,
+    z-strip schedule and number of right-hand sides per sweep (all, 1, 3, 4,
+    5), 7 right-hand sides (not a multiple of most of these), both output parities, dagger, complex boundary phases and the
+    axpy epilogue, against the oracle on the rounded inputs."""
+    nrhs = 7
+    print(f"lds form fmt={fmt_t} dims={dims}", flush=True)
+    phases = tuple(np.exp(1j * np.array([0.4, -1.1, 2.0, 2.9])))
+    sp, lp, reals = fmt_t
+    fmt = Format(sp, lp, reals)
+    lat = Lattice(dims, 0.126, phases)
+    u = inputs.gen_gauge(dims, 0.5, 740)
+    psi = inputs.gen_spinor_half(dims, 741, nrhs=nrhs)
+    y = inputs.gen_spinor_half(dims, 742, nrhs=nrhs)
+    u_d, x_d, y_d = lat.pack_gauge(to_device(u), fmt), lat.pack_spinor(to_device(psi), fmt), \
+        lat.pack_spinor(to_device(y), fmt)
+    u_o, psi_o, y_o = link_as_stored(u, lp, reals), ROUND[sp](psi), ROUND[sp](y)
+    ph = np.array(phases, dtype=np.complex128)
+    want = {(par, dag): [W.hop_eo(u_o, psi_o[r], 1 - par, ph, dagger=dag) for r in range(nrhs)]
+            for par in (0, 1) for dag in (False, True)}
+    for shape in LDS_SHAPES:
+        assert WE.weo_set_mrhs_shape(*shape) == WE.WEO_OK
+        for (par, dag), ref in want.items():
+            out = lat.hop(u_d, x_d, fmt, out_parity=par, dagger=dag, nrhs=nrhs)
+            got = lat.unpack_spinor(out, fmt, nrhs=nrhs).cpu().numpy()
+            for r in range(nrhs):
+                assert rel_err(got[r], ref[r]) <= TOL[sp], (shape, par, dag, r, rel_err(got[r], ref[r]))
+        out = lat.hop_axpy(u_d, x_d, y_d, fmt, out_parity=1, alpha=-0.3, nrhs=nrhs)
+        got = lat.unpack_spinor(out, fmt, nrhs=nrhs).cpu().numpy()
+        for r in range(nrhs):
+            assert rel_err(got[r], y_o[r] - 0.3 * want[(1, False)][r]) <= TOL[sp], (shape, "axpy", r)
+
+
+@pytest.mark.parametrize("fmt_t", [("f64", "f64", 12), ("f32", "f32", 18)], ids=["f64-12", "f32-18"])
+def test_lds_form_in_solver(fmt_t):
+    """Twelve sources solved by CGLS with the LDS form forced for every
+    multi-rhs hop (its norm partials drive the solver): every solution's
+    oracle residual meets the tolerance."""
+    from paper_2303_08609_amd.solve import cg
+    print(f"lds form in solver fmt={fmt_t}", flush=True)
+    dims, kappa = (8, 8, 8, 8), 0.126
+    fmt = Format(*fmt_t)
+    lat = Lattice(dims, kappa, AP)
+    u = inputs.gen_gauge(dims, 0.5, 401)
+    b = inputs.gen_point_noise_sources(dims, 406)
+    assert WE.weo_set_mrhs_shape(-5, 4, 0, 0, 0) == WE.WEO_OK
+    tol = 1e-10 if fmt_t[0] == "f64" else 1e-5
+    x_p, info = cg(lat, fmt, lat.pack_gauge(to_device(u), fmt), lat.pack_spinor(to_device(b), fmt), nrhs=12,
+                   tol=tol, maxiter=5000)
+    assert info["status"] == WE.WEO_OK, info
+    x = lat.unpack_spinor(x_p, fmt, nrhs=12).cpu().numpy()
+    u_o, ph = link_as_stored(u, fmt_t[1], fmt_t[2]), np.array(AP, dtype=np.complex128)
+    for r in range(12):
+        br = ROUND[fmt_t[0]](b[r])
+        res = br - W.apply_m(u_o, x[r], kappa, ph)
+        assert np.linalg.norm(res) / np.linalg.norm(br) <= 3 * tol, r
+
+
 @pytest.mark.parametrize("nrhs", [2, 5, 12, 16])
 def test_tuned_apply_matches_oracle(nrhs):
     dims = (8, 4, 6, 4)
@@ -115,6 +183,11 @@ def test_bad_shape_rejected():
     assert WE.weo_set_mrhs_shape(2, 64, 2, 0, 0) == WE.WEO_ERR_ARG
     assert WE.weo_set_mrhs_shape(2, 64, 0, -1, 0) == WE.WEO_ERR_ARG
     assert WE.weo_set_mrhs_shape(2, 64, 0, 0, 2) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(-5, 5, 0, 0, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(-5, 64, 0, 0, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(-5, 4, 0, 0, 17) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(-5, 4, 0, 0, -1) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(-6, 64, 0, 0, 0) == WE.WEO_ERR_ARG
 
 
 def test_in_place_axpy_on_an_untuned_shape():

@@ -269,3 +269,47 @@ def test_even_odd_needs_fewer_iterations_than_dw(fmt):
     for sol in (got_full, got_eo):
         r = eta_r - W.dirac_wilson(link_as_stored(u, fmt.link, fmt.link_reals), sol, kappa, ph)
         assert np.linalg.norm(r) / np.linalg.norm(eta_r) < (1e-9 if fmt is F64 else 1e-4)
+
+
+def test_defect_correction_drops_converged_rhs(capfd, monkeypatch):
+    """Four sources under FP64 defect correction around FP16 12-real-link
+    inner solves, started from: zero (rhs 0 and 2), an FP64 solution to 1e-12
+    (rhs 1: converged before any inner solve), the same solution perturbed to
+    about 1e-6 (rhs 3: fewer steps than the zero starts).  The steps after
+    one converges run on the live ones only (the log shows the live count
+    falling); every returned solution has an oracle residual <= 1e-10 and
+    equals the one-at-a-time solution to the solves' accuracy."""
+    print("dc with staggered convergence", flush=True)
+    dims, kappa = (8, 8, 8, 16), 0.1265
+    u = inputs.gen_gauge(dims, 0.7, 311)
+    b = np.stack([inputs.gen_spinor_half(dims, 312 + r) for r in range(4)])
+    lat = Lattice(dims, kappa, AP)
+    u_dev = to_device(u)
+    u64 = lat.pack_gauge(u_dev, F64)
+    f16 = Format("f16", "f16", 12)
+    u16 = lat.pack_gauge(u_dev, f16)
+    xs, _ = cg(lat, F64, u64, lat.pack_spinor(to_device(b[1]), F64), tol=1e-12, maxiter=5000)
+    x1 = lat.unpack_spinor(xs, F64).cpu().numpy()
+    rng = np.random.default_rng(5)
+    x0 = np.zeros_like(b)
+    x0[1] = x1
+    x0[3] = x1 + 1e-6 * np.linalg.norm(x1) / np.sqrt(x1.size) * rng.standard_normal(x1.shape)
+    b[3] = b[1]
+    monkeypatch.setenv("WILSON_EO_LOG", "1")
+    x_p, info = cg(lat, F64, u64, lat.pack_spinor(to_device(b), F64), nrhs=4, tol=1e-10, inner=f16, u_inner=u16,
+                   inner_tol=1e-3, max_outer=60, maxiter=20000, method="bicgstab",
+                   x0=lat.pack_spinor(to_device(x0), F64))
+    monkeypatch.delenv("WILSON_EO_LOG")
+    log = [l for l in capfd.readouterr().err.splitlines() if l.startswith("[wilson_eo] outer")]
+    print("\n".join(log), flush=True)
+    assert info["status"] == WE.WEO_OK, info
+    live = [int(l.split(":")[1].split()[0]) for l in log]
+    assert live[0] == 3 and live[-1] == 0 and min(live[1:-1] or [3]) < 3, live
+    x = lat.unpack_spinor(x_p, F64, nrhs=4).cpu().numpy()
+    for r in range(4):
+        assert _oracle_resid(u, x[r], b[r], kappa) <= 1e-10, r
+    for r in (0, 2):
+        xr, _ = cg(lat, F64, u64, lat.pack_spinor(to_device(b[r]), F64), tol=1e-10, inner=f16, u_inner=u16,
+                   inner_tol=1e-3, max_outer=60, maxiter=20000, method="bicgstab")
+        assert rel_err(x[r], lat.unpack_spinor(xr, F64).cpu().numpy()) < 1e-8, r
+    assert rel_err(x[1], x1) < 1e-11
