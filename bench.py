@@ -31,7 +31,8 @@ The JSON line also carries:
                 one source at 48^3x96.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--format f32/f32/18]
-                    [--no-solve] [--no-cpu] [--profile-mode]
+                    [--no-solve] [--no-cpu] [--profile-mode | --profile-solve | --profile-split |
+                     --profile-shapes]
 """
 from __future__ import annotations
 
@@ -59,6 +60,13 @@ EPS = 0.5
 SEED_GAUGE, SEED_SRC = 201, 202
 FLOP_SITE = 1320
 REAL = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+# Launch shapes of --profile-shapes (weo_set_mrhs_shape arguments): the packed
+# FP16 link-resident kernel in several workgroup sizes and schedules, the
+# LDS-staged kernel, and one lane per (site, rhs).
+PROFILE_SHAPES = [(-4, 256, 0, 8, 0), (-4, 256, 0, 0, 0), (-4, 64, 0, 8, 0), (-4, 64, 1, 8, 0), (-4, 256, 1, 2, 0),
+                  (-2, 256, 0, 8, 0), (-5, 2, 0, 4, 0), (-5, 8, 0, 4, 0), (1, 0, 0, 0, 0)]
 
 
 def hop_bytes_per_site(sp, lp, reals):
@@ -272,6 +280,9 @@ def main():
     ap.add_argument("--profile-split", action="store_true",
                     help="short fixed run for rocprofv3: one device's share of the t-split hop at "
                          "32^3x8, sequential and with the face pack on a second stream, --steps each")
+    ap.add_argument("--profile-shapes", action="store_true",
+                    help="short fixed run for rocprofv3 --pmc: the FP16/12 multi-rhs hop at 32^3x64 in "
+                         "fixed launch shapes for 12, 6 and 3 right-hand sides, 3 launches each")
     ap.add_argument("--profile-mode", action="store_true",
                     help="short fixed run for rocprofv3: a 1 GiB device copy (counter "
                          "calibration) and --steps hop launches per format, nothing else")
@@ -287,10 +298,10 @@ def main():
 
     torch.cuda.set_device(0)
     if a.profile_solve:
-        from paper_2303_08609_amd.solve import cg
+        from paper_2303_08609_amd.solve import F64_OUTER, cg
         lat12 = Lattice(DIMS, KAPPA, (1, 1, 1, -1))
         ud = to_device(inputs.gen_gauge(DIMS, EPS, 401))
-        f64, fi = Format("f64", "f64", 18), Format(*parse_fmt(a.solve_inner))
+        f64, fi = Format(*F64_OUTER), Format(*parse_fmt(a.solve_inner))
         u64, ui = lat12.pack_gauge(ud, f64), lat12.pack_gauge(ud, fi)
         b12 = lat12.pack_spinor(to_device(inputs.gen_point_noise_sources(DIMS, 406)), f64)
         for k in range(2):
@@ -300,6 +311,22 @@ def main():
             torch.cuda.synchronize()
             print(f"[bench] profiled 12-rhs solve {k}: {info['seconds']:.4f} s, inner {info['iters']}, "
                   f"outer {info['outer_iters']}", file=sys.stderr, flush=True)
+        return
+    if a.profile_shapes:
+        from paper_2303_08609_amd import wilson_eo as WE
+        lat12 = Lattice(DIMS, KAPPA, (1, 1, 1, -1))
+        f2 = Format("f16", "f16", 12)
+        ud = lat12.pack_gauge(to_device(inputs.gen_gauge(DIMS, EPS, 401)), f2)
+        xd = lat12.pack_spinor(to_device(inputs.gen_point_noise_sources(DIMS, 406)), f2)
+        out = lat12.new_spinor(f2, 12)
+        for sh in PROFILE_SHAPES:
+            WE.check(WE.weo_set_mrhs_shape(*sh), "weo_set_mrhs_shape")
+            for nr in (12, 6, 3):
+                for _ in range(3):
+                    lat12.hop(ud, xd, f2, out_parity=1, nrhs=nr, out=out)
+                torch.cuda.synchronize()
+                print(f"[bench] profiled shape {sh}, {nr} rhs", file=sys.stderr, flush=True)
+        WE.weo_set_mrhs_shape(0, 0, 0, 0, 0)
         return
     if a.profile_split:
         sdims = (32, 32, 32, 8)
