@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_ho
     const int rhs = blockIdx.y;
     const uint8_t* in = P.in + (size_t)rhs * P.spinor_bytes;
     uint8_t* out = P.out + (size_t)rhs * P.spinor_bytes;
-    double nrm = 0.0;
+    double nrm = 0.0, dre = 0.0, dim = 0.0;
     if (ih < P.g.vh) {
         const Site s = decode(P.g, ih, P.out_par);
         const Nbr nb = neighbours(P.g, s);
@@ -40,26 +40,12 @@ __global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_ho
         }
         if constexpr (AXPY) hop_addends<SP>(P, (size_t)rhs, ih, acc);
         store_rec<SP, 12, C, hop_nt_store<SP>()>(out, P.g.vh, ih, acc);
-        if constexpr (NORM) {
-            // norm of the value as stored (rounded to the storage precision)
-            C st[12];
-            if constexpr (SP == P_F64 || SP == P_F32) {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) st[k] = acc[k];
-            } else {
-                round_rec<SP, 12>(acc, st);
-            }
-#pragma unroll
-            for (int k = 0; k < 12; ++k)
-                nrm += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
-        }
+        if constexpr (NORM) hop_reduce<SP>(P, (size_t)rhs, ih, acc, nrm, dre, dim);
     }
     if constexpr (NORM) {
         // one partial per 64-site chunk (one wavefront)
-        const double s = wave_sum64(nrm);
         const uint32_t chunk = (block_first_site(P.sched, P.g, blk, blockDim.x) + (threadIdx.x & ~63u)) >> 6;
-        const uint32_t nchunk = (P.g.vh + 63) >> 6;
-        if ((threadIdx.x & 63) == 0 && chunk < nchunk) P.partial[(size_t)rhs * nchunk + chunk] = s;
+        hop_partials_out(P, (size_t)rhs, chunk, (P.g.vh + 63) >> 6, (threadIdx.x & 63) == 0, nrm, dre, dim);
     }
 }
 
@@ -126,6 +112,10 @@ hipError_t launch_hop_single(const HopLaunch& h, hipStream_t s) {
     P.y = static_cast<const uint8_t*>(h.y);
     P.z = static_cast<const uint8_t*>(h.z);
     P.cy = h.cy;
+    P.dmode = h.dmode;
+    P.dw = static_cast<const uint8_t*>(h.dw);
+    P.pdre = h.pdre;
+    P.pdim = h.pdim;
     P.alpha = h.alpha;
     P.partial = h.partial;
     P.spinor_bytes = spinor_field_bytes(h.g, h.fmt);

@@ -143,8 +143,11 @@ hipError_t launch_hop_clover(const HopLaunch& h, const void* clv, hipStream_t s)
     P.in = static_cast<const uint8_t*>(h.in);
     P.out = static_cast<uint8_t*>(h.out);
     P.y = static_cast<const uint8_t*>(h.y);
-    P.z = nullptr;            // the clover epilogue takes y only
+    P.z = nullptr;            // the clover epilogue takes y only, no fused dot
     P.cy = 1.0;
+    P.dmode = 0;
+    P.dw = nullptr;
+    P.pdre = P.pdim = nullptr;
     P.alpha = h.alpha;
     P.partial = h.partial;
     P.spinor_bytes = spinor_field_bytes(h.g, h.fmt);

@@ -104,6 +104,12 @@ struct HopParams {
     const uint8_t* y;       // axpy addend (parity out_par) or null
     const uint8_t* z;       // second addend (with y only) or null
     double cy;              // coefficient of y
+    // fused dot with the output (needs partial): dmode 1: <dw, out>,
+    // 2: <out, y>; real and imaginary partials per 64 sites into pdre, pdim
+    int dmode;
+    const uint8_t* dw;
+    double* pdre;
+    double* pdim;
     double alpha;
     double* partial;
     size_t spinor_bytes;    // bytes of one packed spinor field
@@ -131,6 +137,50 @@ __device__ __forceinline__ void hop_addends(const HopParams& P, size_t r, uint32
         for (int k = 0; k < 12; ++k) {
             acc[k].x += zv[k].x;
             acc[k].y += zv[k].y;
+        }
+    }
+}
+
+// Per-lane contributions of the output record acc (rhs r, site ih) to the
+// fused reductions, taken on the value as stored (rounded to SP): ||out||^2
+// and, with P.dmode, the complex dot <dw, out> = sum conj(dw) out (1) or
+// <out, y> = sum conj(out) y (2).
+template <int SP, class C>
+__device__ __forceinline__ void hop_reduce(const HopParams& P, size_t r, uint32_t ih, const C* acc, double& nrm,
+                                           double& dre, double& dim) {
+    C st[12];
+    if constexpr (SP == P_F64 || SP == P_F32) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) st[k] = acc[k];
+    } else {
+        round_rec<SP, 12>(acc, st);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) nrm += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
+    if (P.dmode) {
+        C w[12];
+        load_rec<SP, 12>((P.dmode == 1 ? P.dw : P.y) + r * P.spinor_bytes, P.g.vh, ih, w);
+        const double sg = P.dmode == 1 ? 1.0 : -1.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double ox = st[k].x, oy = st[k].y, wx = w[k].x, wy = w[k].y;
+            dre += ox * wx + oy * wy;
+            dim += sg * (wx * oy - wy * ox);
+        }
+    }
+}
+
+// The wavefront's sums of hop_reduce for rhs r into the partial arrays (one
+// entry per 64 sites); every lane of the wavefront calls it.
+__device__ __forceinline__ void hop_partials_out(const HopParams& P, size_t r, uint32_t chunk, uint32_t nchunk,
+                                                 bool lead, double nrm, double dre, double dim) {
+    const double t = wave_sum64(nrm);
+    if (lead && chunk < nchunk) P.partial[r * nchunk + chunk] = t;
+    if (P.dmode) {
+        const double a = wave_sum64(dre), b = wave_sum64(dim);
+        if (lead && chunk < nchunk) {
+            P.pdre[r * nchunk + chunk] = a;
+            P.pdim[r * nchunk + chunk] = b;
         }
     }
 }

@@ -143,9 +143,9 @@ __global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
         const uint32_t blk = xcd_block(b, M.nblk, P.remap);
         const uint32_t base = block_first_site(P.sched, P.g, blk, S);
         const uint32_t ih = base + threadIdx.x;
-        double nrm[NR];
+        double nrm[NR], dre[NR], dim[NR];
 #pragma unroll
-        for (int q = 0; q < NR; ++q) nrm[q] = 0.0;
+        for (int q = 0; q < NR; ++q) nrm[q] = dre[q] = dim[q] = 0.0;
         if (ih < P.g.vh && r0 < M.nrhs) {
             const Site s = decode(P.g, ih, P.out_par);
             const Nbr nb = neighbours(P.g, s);
@@ -173,29 +173,17 @@ __global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
                     if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc[q]);
                     uint8_t* out = P.out + (size_t)r * P.spinor_bytes;
                     store_rec<SP, 12, C, hop_nt_store<SP>()>(out, P.g.vh, ih, acc[q]);
-                    if (P.partial) {
-                        C st[12];
-                        if constexpr (SP == P_F64 || SP == P_F32) {
-#pragma unroll
-                            for (int k = 0; k < 12; ++k) st[k] = acc[q][k];
-                        } else {
-                            round_rec<SP, 12>(acc[q], st);
-                        }
-#pragma unroll
-                        for (int k = 0; k < 12; ++k)
-                            nrm[q] += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
-                    }
+                    if (P.partial) hop_reduce<SP>(P, (size_t)r, ih, acc[q], nrm[q], dre[q], dim[q]);
                 }
             }
         }
         if (P.partial) {
             const uint32_t chunk = (base + (threadIdx.x & ~63u)) >> 6;
 #pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                const double t = wave_sum64(nrm[q]);
-                if ((threadIdx.x & 63) == 0 && chunk < nchunk && r0 + q < M.nrhs)
-                    P.partial[(size_t)(r0 + q) * nchunk + chunk] = t;
-            }
+            for (int q = 0; q < NR; ++q)
+                if (r0 + q < M.nrhs)          // wave-uniform
+                    hop_partials_out(P, (size_t)(r0 + q), chunk, nchunk, (threadIdx.x & 63) == 0, nrm[q], dre[q],
+                                     dim[q]);
         }
     }
 }
@@ -289,7 +277,7 @@ __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
             for (int k = 0; k < D; ++k) ring[k].load(P.in, n, nb.i[k]);
         }
         for (int r = 0; r < M.nrhs; ++r) {
-            double nrm = 0.0;
+            double nrm = 0.0, dre = 0.0, dim = 0.0;
             if (valid) {
                 // keep the links as raw words across the loop: without this the
                 // compiler hoists their conversion out of it and spills
@@ -305,24 +293,11 @@ __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
                 lr_step<SP, LP, L12, DAG, CPH, D, 0>(P, in, in_next, nb, lk, ring, acc);
                 if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc);
                 store_rec<SP, 12>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
-                if (P.partial) {
-                    C st[12];
-                    if constexpr (SP == P_F32) {
-#pragma unroll
-                        for (int k = 0; k < 12; ++k) st[k] = acc[k];
-                    } else {
-                        round_rec<SP, 12>(acc, st);
-                    }
-#pragma unroll
-                    for (int k = 0; k < 12; ++k)
-                        nrm += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
-                }
+                if (P.partial) hop_reduce<SP>(P, (size_t)r, ih, acc, nrm, dre, dim);
             }
-            if (P.partial) {
-                const double t = wave_sum64(nrm);
-                const uint32_t chunk = (base + (threadIdx.x & ~63u)) >> 6;
-                if ((threadIdx.x & 63) == 0 && chunk < nchunk) P.partial[(size_t)r * nchunk + chunk] = t;
-            }
+            if (P.partial)
+                hop_partials_out(P, (size_t)r, (base + (threadIdx.x & ~63u)) >> 6, nchunk, (threadIdx.x & 63) == 0, nrm,
+                                 dre, dim);
         }
     }
 }
@@ -453,7 +428,7 @@ __global__ void __launch_bounds__(64 * lw_maxw<SP>()) k_hop_lw(const MrhsParams 
             }
         }
         for (int r = r0 + wv; r < r1; r += W) {
-            double nrm = 0.0;
+            double nrm = 0.0, dre = 0.0, dim = 0.0;
             if (valid) {
                 const uint8_t* in = P.in + (size_t)r * P.spinor_bytes;
                 if constexpr (!lw_cross<SP>()) {
@@ -475,24 +450,9 @@ __global__ void __launch_bounds__(64 * lw_maxw<SP>()) k_hop_lw(const MrhsParams 
                 lw_step<SP, LP, L12, DAG, CPH, D, 0>(P, lds, lo, in, in_next, nb, ring, acc);
                 if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc);
                 store_rec<SP, 12, C, hop_nt_store<SP>()>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
-                if (P.partial) {
-                    C st[12];
-                    if constexpr (SP == P_F64 || SP == P_F32) {
-#pragma unroll
-                        for (int k = 0; k < 12; ++k) st[k] = acc[k];
-                    } else {
-                        round_rec<SP, 12>(acc, st);
-                    }
-#pragma unroll
-                    for (int k = 0; k < 12; ++k)
-                        nrm += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
-                }
+                if (P.partial) hop_reduce<SP>(P, (size_t)r, ih, acc, nrm, dre, dim);
             }
-            if (P.partial) {
-                const double t = wave_sum64(nrm);
-                const uint32_t chunk = base >> 6;
-                if (lane == 0 && chunk < nchunk) P.partial[(size_t)r * nchunk + chunk] = t;
-            }
+            if (P.partial) hop_partials_out(P, (size_t)r, base >> 6, nchunk, lane == 0, nrm, dre, dim);
         }
     }
 }
@@ -693,7 +653,7 @@ __global__ void __launch_bounds__(256) k_hop_lr16(const MrhsParams M) {
             for (int k = 0; k < D; ++k) ring[k].load(P.in, n, nb.i[k]);
         }
         for (int r = 0; r < M.nrhs; ++r) {
-            double nrm = 0.0;
+            double nrm = 0.0, dre = 0.0, dim = 0.0;
             if (valid) {
                 // keep the link words as they are across the loop
 #pragma unroll
@@ -708,19 +668,11 @@ __global__ void __launch_bounds__(256) k_hop_lr16(const MrhsParams M) {
                 h16_step<DAG, D, 0>(P, in, in_next, nb, lk, ring, acc);
                 if (P.y) hop_addends<P_F16>(P, (size_t)r, ih, acc);
                 store_rec<P_F16, 12>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
-                if (P.partial) {
-                    float2 st[12];
-                    round_rec<P_F16, 12>(acc, st);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k)
-                        nrm += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
-                }
+                if (P.partial) hop_reduce<P_F16>(P, (size_t)r, ih, acc, nrm, dre, dim);
             }
-            if (P.partial) {
-                const double t = wave_sum64(nrm);
-                const uint32_t chunk = (base + (threadIdx.x & ~63u)) >> 6;
-                if ((threadIdx.x & 63) == 0 && chunk < nchunk) P.partial[(size_t)r * nchunk + chunk] = t;
-            }
+            if (P.partial)
+                hop_partials_out(P, (size_t)r, (base + (threadIdx.x & ~63u)) >> 6, nchunk, (threadIdx.x & 63) == 0, nrm,
+                                 dre, dim);
         }
     }
 }
@@ -738,6 +690,10 @@ static HopParams hop_params(const HopLaunch& h) {
     P.y = static_cast<const uint8_t*>(h.y);
     P.z = static_cast<const uint8_t*>(h.z);
     P.cy = h.cy;
+    P.dmode = h.dmode;
+    P.dw = static_cast<const uint8_t*>(h.dw);
+    P.pdre = h.pdre;
+    P.pdim = h.pdim;
     P.alpha = h.alpha;
     P.partial = h.partial;
     P.spinor_bytes = spinor_field_bytes(h.g, h.fmt);
@@ -1173,7 +1129,8 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
         if (c.nr > h.nrhs) c.nr = h.nrhs;
         return c.nr <= 1 ? launch_hop_single(h, s) : launch_hop_mrhs(h, c, s);
     }
-    const int epi = (h.y != nullptr ? 1 : 0) + (h.partial != nullptr ? 2 : 0) + (h.z != nullptr ? 4 : 0);
+    const int epi = (h.y != nullptr ? 1 : 0) + (h.partial != nullptr ? 2 : 0) + (h.z != nullptr ? 4 : 0) +
+                    (h.dmode != 0 ? 8 : 0);
     const TuneKey key{h.g.lx, h.g.ly, h.g.lz, h.g.lt, h.fmt, h.nrhs, epi};
     TuneEntry e;
     bool have = false;

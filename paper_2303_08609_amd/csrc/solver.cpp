@@ -206,7 +206,9 @@ struct Ctx {
 
 // out = A in with A = M (dagger 0) or M^dag (dagger 1); partial = ||out||^2.
 hipError_t apply_m(Ctx& c, int fmt, const void* u, int dagger, const void* in, void* out, void* tmp,
-                   int nrhs, double* partial) {
+                   int nrhs, double* partial, int dmode = 0, const void* dw = nullptr, double* pdre = nullptr,
+                   double* pdim = nullptr) {
+    if (c.clv && dmode) return hipErrorInvalidValue;     // the site-block hops fuse no dot
     if (c.clv) {
         ++c.applies;
         return launch_apply_clover(c.g, fmt, c.ph, c.lat->kappa, dagger, u, c.clv, in, out, tmp, nrhs, partial,
@@ -233,6 +235,10 @@ hipError_t apply_m(Ctx& c, int fmt, const void* u, int dagger, const void* in, v
     h.y = in;
     h.alpha = -c.lat->kappa * c.lat->kappa;
     h.partial = partial;
+    h.dmode = dmode;
+    h.dw = dw;
+    h.pdre = pdre;
+    h.pdim = pdim;
     ++c.applies;
     return launch_hop(h, c.st);
 }
@@ -500,14 +506,33 @@ int run_level_bicg(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, 
     if (!live) return WEO_OK;
     LookPlan plan(check_every, ss);
     int look = plan.first();
+    // Wilson M with every vector in one format: <r^, v> and (<t, s>, ||t||^2)
+    // come from the epilogues of the operator's second hop (the dot partner
+    // r^ read there, s being that hop's own axpy input).  With a narrower
+    // operator format (FP16 / BF16 inner solves) both stay separate passes:
+    // omega from the rounded s cost iterations, and the partner read in the
+    // epilogue of the packed FP16 hop cost more than the pass it saves.
+    const bool fuse = op == WEO_OP_M && !c.clv && !c.full && same;
+    const bool fuse_ts = fuse;
+    const int nbh = (int)c.nb_apply;
     for (int it = 1; it <= maxiter; ++it) {
-        HIPCHK(apply_op(c, op, fmt_op, u, w.p, w.q, w.r, w.tmp, nrhs, nullptr));
-        HIPCHK(launch_bi_cdot(g, fmt_op, fmt_op, nrhs, w.sc.mask, w.rh, w.q, w.pa, w.pb, c.st));
-        HIPCHK(launch_bi_scalars(BI_ALPHA, B, nbb, w.pa, w.pb, nullptr, c.st));
+        if (fuse) {
+            HIPCHK(apply_m(c, fmt_op, u, 0, w.p, w.q, w.tmp, nrhs, w.pc, 1, w.rh, w.pa, w.pb));
+            HIPCHK(launch_bi_scalars(BI_ALPHA, B, nbh, w.pa, w.pb, nullptr, c.st));
+        } else {
+            HIPCHK(apply_op(c, op, fmt_op, u, w.p, w.q, w.r, w.tmp, nrhs, nullptr));
+            HIPCHK(launch_bi_cdot(g, fmt_op, fmt_op, nrhs, w.sc.mask, w.rh, w.q, w.pa, w.pb, c.st));
+            HIPCHK(launch_bi_scalars(BI_ALPHA, B, nbb, w.pa, w.pb, nullptr, c.st));
+        }
         HIPCHK(launch_bi_s(g, fmt_acc, fmt_op, nrhs, B, w.s_acc, w.q, w.s2, s_op, w.pc, c.st));
-        HIPCHK(apply_op(c, op, fmt_op, u, s_op, w.t, w.r, w.tmp, nrhs, nullptr));
-        HIPCHK(launch_bi_ts(g, fmt_acc, fmt_op, nrhs, w.sc.mask, w.t, w.s2, w.pa, w.pb, w.pc, c.st));
-        HIPCHK(launch_bi_scalars(BI_OMEGA, B, nbb, w.pa, w.pb, w.pc, c.st));
+        if (fuse_ts) {
+            HIPCHK(apply_m(c, fmt_op, u, 0, s_op, w.t, w.tmp, nrhs, w.pc, 2, nullptr, w.pa, w.pb));
+            HIPCHK(launch_bi_scalars(BI_OMEGA, B, nbh, w.pa, w.pb, w.pc, c.st));
+        } else {
+            HIPCHK(apply_op(c, op, fmt_op, u, s_op, w.t, w.r, w.tmp, nrhs, nullptr));
+            HIPCHK(launch_bi_ts(g, fmt_acc, fmt_op, nrhs, w.sc.mask, w.t, w.s2, w.pa, w.pb, w.pc, c.st));
+            HIPCHK(launch_bi_scalars(BI_OMEGA, B, nbb, w.pa, w.pb, w.pc, c.st));
+        }
         HIPCHK(launch_bi_xr(g, fmt_acc, fmt_op, nrhs, B, x_acc, w.p, w.s2, w.t, w.s_acc, w.rh, w.pa, w.pb,
                             w.pc, c.st));
         HIPCHK(launch_bi_scalars(BI_BETA, B, nbb, w.pa, w.pb, w.pc, c.st));

@@ -47,6 +47,12 @@ struct HopLaunch {
     // the axpy of M; cy = -1 with z = b gives the residual b - M x in one pass
     const void* z = nullptr;
     double cy = 1.0;
+    // fused dot with the output, with partial set: dmode 1: <dw, out>,
+    // 2: <out, y>; real / imaginary partials laid out like partial
+    int dmode = 0;
+    const void* dw = nullptr;
+    double* pdre = nullptr;
+    double* pdim = nullptr;
 };
 
 struct TuneCfg {

@@ -301,6 +301,19 @@ def bench_solves_12rhs(dims=(32, 32, 32, 64), kappa=0.126, eps=0.5, seed_gauge=4
         del ui
     _speedups(out, "fp32_inner_sequential",
               [k for k in out if "fp32" in k and isinstance(out[k], dict)])
+    # the inner tolerance of the FP16 BiCGStab path: each outer step gains
+    # at most about 1e-3 in FP16, and which tolerance needs the fewest
+    # steps and stragglers is data-dependent, so the sweep is reported
+    f16 = Format("f16", "f16", 12)
+    u16 = lat.pack_gauge(ud, f16)
+    sweep = {}
+    for tin in (1e-3, 5e-4, 2e-4, 1e-4):
+        dt, (x, info), runs = _median(lambda: cg(lat, f64, u64, b64, nrhs=12, tol=1e-10, inner=f16, u_inner=u16,
+                                                 inner_tol=tin, maxiter=50000, max_outer=100, method="bicgstab"))
+        sweep[f"{tin:g}"] = {"seconds": round(dt, 4), "runs": runs, "inner_iters": info["iters"],
+                             "outer_iters": info["outer_iters"],
+                             "worst_true_rel_resid": max(info["true_rel_resid"][:12])}
+    out["f16_f16link12_bicgstab_inner_tol_sweep"] = sweep
     return out
 
 
