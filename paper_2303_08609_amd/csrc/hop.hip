@@ -11,7 +11,7 @@ namespace weo {
 template <int SP> struct Waves { static constexpr int n = WEO_WAVES_F32; };
 template <> struct Waves<P_F64> { static constexpr int n = WEO_WAVES_F64; };
 
-template <int SP, int LP, bool L12, bool DAG, bool AXPY, bool NORM, bool CPH>
+template <int SP, int LP, bool L12, bool DAG, bool AXPY, bool NORM, bool CPH, bool DOT = false>
 __global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_hop(const HopParams P) {
     using R = typename Arith<SP>::R;
     using C = cx<R>;
@@ -40,12 +40,12 @@ __global__ void __launch_bounds__(256, Waves<SP>::n > 0 ? Waves<SP>::n : 1) k_ho
         }
         if constexpr (AXPY) hop_addends<SP>(P, (size_t)rhs, ih, acc);
         store_rec<SP, 12, C, hop_nt_store<SP>()>(out, P.g.vh, ih, acc);
-        if constexpr (NORM) hop_reduce<SP>(P, (size_t)rhs, ih, acc, nrm, dre, dim);
+        if constexpr (NORM) hop_reduce<SP, DOT>(P, (size_t)rhs, ih, acc, nrm, dre, dim);
     }
     if constexpr (NORM) {
         // one partial per 64-site chunk (one wavefront)
         const uint32_t chunk = (block_first_site(P.sched, P.g, blk, blockDim.x) + (threadIdx.x & ~63u)) >> 6;
-        hop_partials_out(P, (size_t)rhs, chunk, (P.g.vh + 63) >> 6, (threadIdx.x & 63) == 0, nrm, dre, dim);
+        hop_partials_out<DOT>(P, (size_t)rhs, chunk, (P.g.vh + 63) >> 6, (threadIdx.x & 63) == 0, nrm, dre, dim);
     }
 }
 
@@ -83,6 +83,19 @@ static hipError_t launch_fmt(const HopLaunch& h, const HopParams& P, dim3 grid, 
     const bool axpy = h.y != nullptr, norm = h.partial != nullptr;
     bool cph = false;
     for (int m = 0; m < 4; ++m) cph = cph || h.phase[m][1] != 0.0;
+    if (h.dmode) {
+        // the fused dot: an M epilogue (axpy and norm) only
+        if (!axpy || !norm) return hipErrorInvalidValue;
+#define WEO_HOP_DOT(D)                                                                                   \
+        if (h.dagger == D) {                                                                             \
+            if (cph) hipLaunchKernelGGL((k_hop<SP, LP, L12, D, true, true, true, true>), grid, block, 0, s, P);   \
+            else hipLaunchKernelGGL((k_hop<SP, LP, L12, D, true, true, false, true>), grid, block, 0, s, P);  \
+            return hipGetLastError();                                                                    \
+        }
+        WEO_HOP_DOT(0) WEO_HOP_DOT(1)
+#undef WEO_HOP_DOT
+        return hipErrorInvalidValue;
+    }
 #define WEO_HOP_CASE(D, A, N)                                                            \
     if (h.dagger == D && axpy == A && norm == N) {                                       \
         if (cph)                                                                          \

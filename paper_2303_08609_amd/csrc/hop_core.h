@@ -104,8 +104,9 @@ struct HopParams {
     const uint8_t* y;       // axpy addend (parity out_par) or null
     const uint8_t* z;       // second addend (with y only) or null
     double cy;              // coefficient of y
-    // fused dot with the output (needs partial): dmode 1: <dw, out>,
-    // 2: <out, y>; real and imaginary partials per 64 sites into pdre, pdim
+    // fused dot with the output (needs partial; kernels built with DOT only):
+    // dmode 1: <dw, out>, 2: <out, y>; real and imaginary partials per 64
+    // sites into pdre, pdim
     int dmode;
     const uint8_t* dw;
     double* pdre;
@@ -145,7 +146,9 @@ __device__ __forceinline__ void hop_addends(const HopParams& P, size_t r, uint32
 // fused reductions, taken on the value as stored (rounded to SP): ||out||^2
 // and, with P.dmode, the complex dot <dw, out> = sum conj(dw) out (1) or
 // <out, y> = sum conj(out) y (2).
-template <int SP, class C>
+// DOT is a compile-time switch: the dot code costs registers even when not
+// taken, which pushed the link-resident kernels to a lower occupancy.
+template <int SP, bool DOT = false, class C>
 __device__ __forceinline__ void hop_reduce(const HopParams& P, size_t r, uint32_t ih, const C* acc, double& nrm,
                                            double& dre, double& dim) {
     C st[12];
@@ -157,7 +160,7 @@ __device__ __forceinline__ void hop_reduce(const HopParams& P, size_t r, uint32_
     }
 #pragma unroll
     for (int k = 0; k < 12; ++k) nrm += (double)st[k].x * (double)st[k].x + (double)st[k].y * (double)st[k].y;
-    if (P.dmode) {
+    if constexpr (DOT) {
         C w[12];
         load_rec<SP, 12>((P.dmode == 1 ? P.dw : P.y) + r * P.spinor_bytes, P.g.vh, ih, w);
         const double sg = P.dmode == 1 ? 1.0 : -1.0;
@@ -172,11 +175,12 @@ __device__ __forceinline__ void hop_reduce(const HopParams& P, size_t r, uint32_
 
 // The wavefront's sums of hop_reduce for rhs r into the partial arrays (one
 // entry per 64 sites); every lane of the wavefront calls it.
+template <bool DOT = false>
 __device__ __forceinline__ void hop_partials_out(const HopParams& P, size_t r, uint32_t chunk, uint32_t nchunk,
                                                  bool lead, double nrm, double dre, double dim) {
     const double t = wave_sum64(nrm);
     if (lead && chunk < nchunk) P.partial[r * nchunk + chunk] = t;
-    if (P.dmode) {
+    if constexpr (DOT) {
         const double a = wave_sum64(dre), b = wave_sum64(dim);
         if (lead && chunk < nchunk) {
             P.pdre[r * nchunk + chunk] = a;

@@ -381,7 +381,7 @@ __device__ __forceinline__ void lw_step(const HopParams& P, const uint4* lds, ui
 }
 
 
-template <int SP, int LP, bool L12, bool DAG, bool CPH>
+template <int SP, int LP, bool L12, bool DAG, bool CPH, bool DOT>
 __global__ void __launch_bounds__(64 * lw_maxw<SP>()) k_hop_lw(const MrhsParams M) {
     using R = typename Arith<SP>::R;
     using C = cx<R>;
@@ -450,9 +450,9 @@ __global__ void __launch_bounds__(64 * lw_maxw<SP>()) k_hop_lw(const MrhsParams 
                 lw_step<SP, LP, L12, DAG, CPH, D, 0>(P, lds, lo, in, in_next, nb, ring, acc);
                 if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc);
                 store_rec<SP, 12, C, hop_nt_store<SP>()>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
-                if (P.partial) hop_reduce<SP>(P, (size_t)r, ih, acc, nrm, dre, dim);
+                if (P.partial) hop_reduce<SP, DOT>(P, (size_t)r, ih, acc, nrm, dre, dim);
             }
-            if (P.partial) hop_partials_out(P, (size_t)r, base >> 6, nchunk, lane == 0, nrm, dre, dim);
+            if (P.partial) hop_partials_out<DOT>(P, (size_t)r, base >> 6, nchunk, lane == 0, nrm, dre, dim);
         }
     }
 }
@@ -790,9 +790,15 @@ template <int SP, int LP, bool L12>
 static hipError_t lw_fmt(const HopLaunch& h, const MrhsParams& M, dim3 grid, dim3 block, hipStream_t s) {
     bool cph = false;
     for (int m = 0; m < 4; ++m) cph = cph || h.phase[m][1] != 0.0;
-#define WEO_LW(DG, CP) hipLaunchKernelGGL((k_hop_lw<SP, LP, L12, DG, CP>), grid, block, 0, s, M)
-    if (h.dagger) { if (cph) WEO_LW(true, true); else WEO_LW(true, false); }
-    else { if (cph) WEO_LW(false, true); else WEO_LW(false, false); }
+#define WEO_LW(DG, CP, DT) hipLaunchKernelGGL((k_hop_lw<SP, LP, L12, DG, CP, DT>), grid, block, 0, s, M)
+    if (h.dmode) {
+        if (!h.partial) return hipErrorInvalidValue;
+        if (h.dagger) { if (cph) WEO_LW(true, true, true); else WEO_LW(true, false, true); }
+        else { if (cph) WEO_LW(false, true, true); else WEO_LW(false, false, true); }
+    } else {
+        if (h.dagger) { if (cph) WEO_LW(true, true, false); else WEO_LW(true, false, false); }
+        else { if (cph) WEO_LW(false, true, false); else WEO_LW(false, false, false); }
+    }
 #undef WEO_LW
     return hipGetLastError();
 }
@@ -905,7 +911,8 @@ std::vector<MrhsCfg> candidates(const HopLaunch& h) {
     std::vector<MrhsCfg> v;
     v.push_back({1, 0, 0, 0, 0});
     const bool wide = fmt_info(h.fmt).spinor_prec == P_F64;
-    if (lr_supported(h.fmt))
+    const bool dot = h.dmode != 0;      // the fused dot: single-rhs and LDS-staged kernels only
+    if (lr_supported(h.fmt) && !dot)
         for (int s : {64, 128, 256})
             for (int persist : {0, 1})
                 for (int bz : {0, 2, 4, 8}) {
@@ -927,7 +934,7 @@ std::vector<MrhsCfg> candidates(const HopLaunch& h) {
     }
     const int nrs[] = {2, 3, 4, 6};
     for (int nr : nrs) {
-        if (nr > h.nrhs || (wide && nr > 3)) continue;
+        if (dot || nr > h.nrhs || (wide && nr > 3)) continue;
         for (int s : {64, 128, 256})
             for (int persist : {0, 1})
                 for (int bz : {0, 2, 4, 8}) {
@@ -1108,6 +1115,7 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t s) {
         forced = g_forced;
     }
     if (forced.nr == 1) return launch_hop_single(h, s);
+    if (h.dmode && forced.nr != 0 && forced.nr != kNrLw) return launch_hop_single(h, s);   // no fused dot there
     if (forced.nr == kNrLw) {
         MrhsCfg c = forced;
         if (c.s > lw_max_waves(h.fmt)) c.s = lw_max_waves(h.fmt);      // the format's most wavefronts
