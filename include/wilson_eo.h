@@ -382,7 +382,11 @@ typedef struct {
                                1: FP64 defect correction (fmt must be F64) with
                                   inner solves in format `inner` on links u_inner */
     weo_format inner;       /* inner format when mixed = 1 */
-    double     inner_tol;   /* relative tolerance of each inner solve */
+    double     inner_tol;   /* relative tolerance of each inner solve; a step
+                               whose inner solve can bring every remaining rhs
+                               to tol with a tolerance down to inner_tol / 8
+                               gets that tighter tolerance.  Right-hand sides
+                               that meet tol leave the later steps. */
     int        max_outer;   /* cap on defect-correction steps */
     int        check_every; /* iterations between host convergence checks (>=1) */
     int        method;      /* WEO_SOLVER_CG, WEO_SOLVER_BICGSTAB or

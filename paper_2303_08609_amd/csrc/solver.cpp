@@ -1255,9 +1255,19 @@ extern "C" int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt, const
             if (!can_compact)
                 for (int j = 0; j < mi; ++j) mask[j] = !(rel[cur[j]] <= p->tol);
             if ((rc = set_mask(c, w, mask)) != WEO_OK) return rc;
+            // The inner tolerance: inner_tol, tightened (down to inner_tol / 8)
+            // for a step whose solve can then bring every live rhs to tol --
+            // one inner solve a little longer instead of one more outer step
+            // for the stragglers (an FP64 residual and a Krylov restart).
+            double worst_live = 0.0;
+            for (int j = 0; j < mi; ++j)
+                if (can_compact || !(rel[cur[slots[j]]] <= p->tol)) worst_live = std::fmax(worst_live, rel[cur[slots[j]]]);
+            double tin = p->inner_tol;
+            const double need = worst_live > 0.0 ? p->tol / worst_live : 1.0;
+            if (need < tin && need >= tin / 8.0) tin = std::fmax(0.5 * need, tin / 8.0);
             LevelResult lr;
             c.clv = p->clover_inner;
-            rc = run_method(c, w, p->method, p->op, inner, kAccF32, u_inner, w.x_acc, mi, p->inner_tol,
+            rc = run_method(c, w, p->method, p->op, inner, kAccF32, u_inner, w.x_acc, mi, tin,
                             p->maxiter - inner_iters, p->check_every, &lr);
             c.clv = p->clover;
             if (rc != WEO_OK) return rc;
