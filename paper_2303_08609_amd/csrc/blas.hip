@@ -372,6 +372,43 @@ __global__ void __launch_bounds__(kBlk) k_bi_cdot(Fields F, const int* __restric
     }
 }
 
+// BiCGStab start in one pass: r^ = p = r rounded to OP; partials ||r||^2
+// (every rhs) and <r^, r> (live rhs; r^ as stored, r in ACC)
+template <int ACC, int OP>
+__global__ void __launch_bounds__(kBlk) k_bi_init(Fields F, const int* __restrict__ mask, const uint8_t* r,
+                                                  uint8_t* rh, uint8_t* p, double* prr, double* pre, double* pim) {
+    using CA = cx<typename AR<ACC>::R>;
+    using CO = cx<typename AR<OP>::R>;
+    const int q = blockIdx.y;
+    const uint32_t i = blockIdx.x * kBlk + threadIdx.x;
+    double rr = 0.0, re = 0.0, im = 0.0;
+    if (i < F.vh) {
+        CA rv[12];
+        load_rec<ACC, 12>(r + (size_t)q * F.fb_acc, F.vh, i, rv);
+        CO ro[12];
+        cvt12(rv, ro);
+        store_rec<OP, 12>(rh + (size_t)q * F.fb_op, F.vh, i, ro);
+        store_rec<OP, 12>(p + (size_t)q * F.fb_op, F.vh, i, ro);
+        rr = norm2_12(rv);
+        if (bi_live(mask, q)) {
+            CO hv[12];
+            round_rec<OP, 12>(ro, hv);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                re += (double)hv[k].x * (double)rv[k].x + (double)hv[k].y * (double)rv[k].y;
+                im += (double)hv[k].x * (double)rv[k].y - (double)hv[k].y * (double)rv[k].x;
+            }
+        }
+    }
+    double out[3];
+    group_sum3(rr, re, im, out);
+    if (threadIdx.x == 0) {
+        prr[(size_t)q * gridDim.x + blockIdx.x] = out[0];
+        pre[(size_t)q * gridDim.x + blockIdx.x] = out[1];
+        pim[(size_t)q * gridDim.x + blockIdx.x] = out[2];
+    }
+}
+
 // s = r - alpha v  [s_op = s];  partial = ||s||^2
 template <int ACC, int OP, bool SOP>
 __global__ void __launch_bounds__(kBlk) k_bi_s(Fields F, BiArgs B, const uint8_t* rv, const uint8_t* v,
@@ -757,6 +794,18 @@ hipError_t launch_bi_s(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const B
     WEO_BI_PAIRS(sp_of(fmt_acc), sp_of(fmt_op),
                  if (sop) hipLaunchKernelGGL((k_bi_s<A_, O_, true>), grid, block, 0, st, F, B, R, V, S, SO, partial);
                  else hipLaunchKernelGGL((k_bi_s<A_, O_, false>), grid, block, 0, st, F, B, R, V, S, SO, partial))
+    return hipGetLastError();
+}
+
+hipError_t launch_bi_init(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const int* mask, const void* r,
+                          void* rh, void* p, double* prr, double* pre, double* pim, hipStream_t st) {
+    const Fields F = fields(g, fmt_acc, fmt_op);
+    const dim3 grid(blas_blocks(g), nrhs), block(kBlk);
+    auto* R = static_cast<const uint8_t*>(r);
+    auto* RH = static_cast<uint8_t*>(rh);
+    auto* Pp = static_cast<uint8_t*>(p);
+    WEO_BI_PAIRS(sp_of(fmt_acc), sp_of(fmt_op),
+                 hipLaunchKernelGGL((k_bi_init<A_, O_>), grid, block, 0, st, F, mask, R, RH, Pp, prr, pre, pim))
     return hipGetLastError();
 }
 

@@ -495,11 +495,8 @@ int run_level_bicg(Ctx& c, const Workspace& w, int op, int fmt_op, int fmt_acc, 
     std::vector<int> mask(nrhs);
     std::vector<double> bb(nrhs);
     HIPCHK(hipMemcpyAsync(bb.data(), w.sc.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.st));
-    // r^ = r (rounded to fmt_op), p = r, rho = <r^, r>
-    HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_op, w.rh, nrhs, nullptr, 0, c.st));
-    HIPCHK(launch_convert(g, fmt_acc, w.s_acc, fmt_op, w.p, nrhs, nullptr, 0, c.st));
-    HIPCHK(launch_norm2(g, fmt_acc, w.s_acc, nrhs, w.pa, c.st));
-    HIPCHK(launch_bi_cdot(g, fmt_op, fmt_acc, nrhs, w.sc.mask, w.rh, w.s_acc, w.pb, w.pc, c.st));
+    // r^ = r (rounded to fmt_op), p = r, rho = <r^, r>, in one pass
+    HIPCHK(launch_bi_init(g, fmt_acc, fmt_op, nrhs, w.sc.mask, w.s_acc, w.rh, w.p, w.pa, w.pb, w.pc, c.st));
     HIPCHK(launch_bi_scalars(BI_INIT, B, nbb, w.pa, w.pb, w.pc, c.st));
     int live = look_at(c, w, nrhs, tol2, bb, ss, mask, res);
     if (live < 0) return live;

@@ -150,6 +150,9 @@ struct BiScalHost {
 // partials of <a, b> (a in fmt_a, b in fmt_b)
 hipError_t launch_bi_cdot(const Geom& g, int fmt_a, int fmt_b, int nrhs, const int* mask, const void* a,
                           const void* b, double* pre, double* pim, hipStream_t st);
+// r^ = p = r (in fmt_op), partials ||r||^2 and <r^, r> (one pass)
+hipError_t launch_bi_init(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const int* mask, const void* r,
+                          void* rh, void* p, double* prr, double* pre, double* pim, hipStream_t st);
 // s = r - alpha v, s_op = s, partial ||s||^2
 hipError_t launch_bi_s(const Geom& g, int fmt_acc, int fmt_op, int nrhs, const BiScalHost& h, const void* r,
                        const void* v, void* s, void* s_op, double* partial, hipStream_t st);
