@@ -27,6 +27,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -970,7 +971,7 @@ bool tuning_verbose() {
 // An entry is used only if its shape is among the current candidates for
 // that key (so a stale or edited file can pick a slower shape, never an
 // invalid launch).  New results are appended, one line per write.
-constexpr int kTuneCacheVersion = 2;
+constexpr int kTuneCacheVersion = 3;
 
 const char* tune_cache_path() {
     const char* p = getenv("WILSON_EO_TUNE_CACHE");
@@ -1042,6 +1043,24 @@ bool is_candidate(const HopLaunch& h, const MrhsCfg& c) {
     return false;
 }
 
+// Average microseconds of reps launches of shape c (after one warm-up).
+hipError_t time_cfg(const HopLaunch& h, const MrhsCfg& c, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps,
+                    float* us) {
+    hipError_t err = run_cfg(h, c, s);                            // warm-up
+    if (err != hipSuccess) return err;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = run_cfg(h, c, s);
+    (void)hipEventRecord(e1, s);
+    if (err != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) return err;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *us = 1000.f * ms / reps;
+    return hipSuccess;
+}
+
+// Every candidate timed briefly (3 launches), then the 4 fastest again over
+// 12 launches each: single short timings vary by several per cent between
+// neighbouring shapes, which had made the choice drift from run to run.
 hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return hipErrorUnknown;
@@ -1049,20 +1068,28 @@ hipError_t tune(const HopLaunch& h, hipStream_t s, TuneEntry* best) {
     best->us = 1e30f;
     best->cfg = {1, 0, 0, 0, 0};
     hipError_t err = hipSuccess;
+    std::vector<std::pair<float, MrhsCfg>> timed;
     for (const MrhsCfg& c : candidates(h)) {
-        if ((err = run_cfg(h, c, s)) != hipSuccess) break;       // warm-up
-        (void)hipEventRecord(e0, s);
-        const int reps = 3;
-        for (int r = 0; r < reps && err == hipSuccess; ++r) err = run_cfg(h, c, s);
-        (void)hipEventRecord(e1, s);
-        if (err != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) break;
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const float us = 1000.f * ms / reps;
+        float us = 0.f;
+        if ((err = time_cfg(h, c, s, e0, e1, 3, &us)) != hipSuccess) break;
         if (tuning_verbose())
             fprintf(stderr, "[weo tune] fmt %d nrhs %d: nr %d sites %d persist %d bz %d split %d -> %.1f us\n",
                     h.fmt, h.nrhs, c.nr, c.s, c.persist, c.bz, c.split, us);
-        if (us < best->us) { best->us = us; best->cfg = c; }
+        timed.push_back({us, c});
+    }
+    if (err == hipSuccess) {
+        std::sort(timed.begin(), timed.end(), [](const std::pair<float, MrhsCfg>& a,
+                                                 const std::pair<float, MrhsCfg>& b) { return a.first < b.first; });
+        const size_t nfinal = timed.size() < 4 ? timed.size() : 4;
+        for (size_t k = 0; k < nfinal; ++k) {
+            float us = 0.f;
+            if ((err = time_cfg(h, timed[k].second, s, e0, e1, 12, &us)) != hipSuccess) break;
+            if (tuning_verbose())
+                fprintf(stderr, "[weo tune] final: nr %d sites %d persist %d bz %d split %d -> %.1f us\n",
+                        timed[k].second.nr, timed[k].second.s, timed[k].second.persist, timed[k].second.bz,
+                        timed[k].second.split, us);
+            if (us < best->us) { best->us = us; best->cfg = timed[k].second; }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
