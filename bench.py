@@ -523,7 +523,7 @@ def main():
         print(f"[bench] 48^3x96 solves: {solve['48^3x96_mixed']}", file=sys.stderr, flush=True)
 
     line = {
-        "metric": "eo-Wilson GFlop/s + % HBM roofline (32^3x64); mixed vs FP32 solve time",
+        "metric": "eo-Wilson GFlop/s + % HBM roofline (32^3\u00d764); mixed vs FP32 solve time",
         "value": round(gflops, 1),
         "unit": "GFlop/s",
         "n_gpus": 1,
