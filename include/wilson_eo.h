@@ -422,7 +422,10 @@ size_t wilson_eo_cg_workspace_bytes(const weo_lattice* lat, const weo_format* fm
  * With WEO_SOLVER_BLOCK_CG the right-hand sides whose start does not already
  * meet the tolerance form one block (the others are left as they are);
  * info->iters counts block iterations; the block method needs FP64 or FP32
- * spinors (else WEO_ERR_FORMAT); dependent residual columns are deflated. */
+ * spinors (else WEO_ERR_FORMAT); dependent residual columns are deflated.
+ * Its Gram matrices run on the vector units; the environment variable
+ * WEO_GRAM=mfma (read per call) moves them to the FP64 matrix cores, which
+ * gives the same results to FP64 rounding but is slower on MI355X. */
 int wilson_eo_cg(const weo_lattice* lat, const weo_format* fmt,
                  const weo_solver_params* p,
                  const void* u, const void* u_inner,

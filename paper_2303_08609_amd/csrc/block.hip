@@ -11,6 +11,8 @@
 // FP64); every workgroup writes one partial matrix and a second kernel sums
 // the partials in a fixed order (deterministic).
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "weo_device.h"
 #include "weo_internal.h"
@@ -132,6 +134,119 @@ __global__ void __launch_bounds__(64 * kMaxCells) k_bgram(uint64_t nch, int s, B
     for (int t = threadIdx.x; t < 2 * s * s; t += blockDim.x) {
         const int j = (t >> 1) / s, k = (t >> 1) % s;
         if ((j >> 2) > (k >> 2)) part[(size_t)t * nwg + blockIdx.x] = 0.0;
+    }
+}
+
+// The same partial Gram sums on the FP64 matrix cores.  A block of s
+// complex fields is read as a tall real matrix X with 2s <= 32 columns
+// (column c < s: the real parts of field c, s <= c < 2s: the imaginary parts
+// of field c - s, the rest zero) and one row per complex component; then
+// R = X_A^T X_B is accumulated by v_mfma_f64_16x16x4f64 in 16 x 16 tiles, four
+// rows per instruction, and
+//     Re <a_j, b_k> = R[j][k] + R[s+j][s+k],  Im <a_j, b_k> = R[j][s+k] - R[s+j][k].
+// Each wavefront walks every (gridDim.x x 8)-th group of four rows, the
+// loads of four groups issued before their products; lane l supplies row
+// l / 16 of column l % 16 (tile 0) and 16 + l % 16 (tile 1) of both
+// operands, and holds rows l / 16 + 4 i (i = 0..3), column l % 16 of each
+// accumulator tile.  FP32 values are exact in FP64.  SAME: b is a
+// (R symmetric: three tiles).
+typedef double gd4 __attribute__((ext_vector_type(4)));
+
+template <int SP>
+__device__ __forceinline__ const uint8_t* gram_col(const BlockRef& X, int s, int c, bool* live) {
+    constexpr int RB = SP == P_F64 ? 8 : 4;          // bytes of one real
+    *live = c < 2 * s;
+    const int f = c < s ? c : (c < 2 * s ? c - s : 0);
+    return reinterpret_cast<const uint8_t*>(col_sel(X, f)) + (c >= s && c < 2 * s ? RB : 0);
+}
+
+template <int SP>
+__device__ __forceinline__ double gram_val(const uint8_t* p, bool live, uint64_t k, uint64_t nrows) {
+    constexpr int CB = SP == P_F64 ? 16 : 8;         // bytes of one complex
+    if (!live || k >= nrows) return 0.0;
+    if constexpr (SP == P_F64) return *reinterpret_cast<const double*>(p + k * CB);
+    else return (double)*reinterpret_cast<const float*>(p + k * CB);
+}
+
+static constexpr int kGramMfmaWaves = 8;    // wavefronts per workgroup of k_bgram_mfma
+static constexpr int kGramMfmaUnroll = 4;   // row groups whose loads are issued together
+
+template <int SP, bool SAME>
+__global__ void __launch_bounds__(64 * kGramMfmaWaves) k_bgram_mfma(uint64_t nch, int s, BlockRef A, BlockRef B,
+                                                                     double* part) {
+    __shared__ double R[32][33];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t nrows = nch * (SP == P_F64 ? 1 : 2);
+    const uint64_t nsteps = (nrows + 3) / 4;
+    bool la0, la1, lb0 = false, lb1 = false;
+    const uint8_t* a0 = gram_col<SP>(A, s, lane & 15, &la0);
+    const uint8_t* a1 = gram_col<SP>(A, s, 16 + (lane & 15), &la1);
+    const uint8_t* b0 = a0;
+    const uint8_t* b1 = a1;
+    if constexpr (!SAME) {
+        b0 = gram_col<SP>(B, s, lane & 15, &lb0);
+        b1 = gram_col<SP>(B, s, 16 + (lane & 15), &lb1);
+    }
+    const bool two = 2 * s > 16;                     // the second column tile is needed
+    gd4 d00 = {0, 0, 0, 0}, d01 = d00, d10 = d00, d11 = d00;
+    const uint64_t stride = (uint64_t)gridDim.x * kGramMfmaWaves;
+    for (uint64_t st = (uint64_t)blockIdx.x * kGramMfmaWaves + wv; st < nsteps; st += kGramMfmaUnroll * stride) {
+        // the loads of several row groups first (each lane's value of its
+        // row and columns), then their products
+        double x0[kGramMfmaUnroll], y0[kGramMfmaUnroll], x1[kGramMfmaUnroll], y1[kGramMfmaUnroll];
+#pragma unroll
+        for (int u = 0; u < kGramMfmaUnroll; ++u) {
+            const uint64_t k = 4 * (st + u * stride) + (uint64_t)(lane >> 4);
+            x0[u] = gram_val<SP>(a0, la0, k, nrows);
+            y0[u] = SAME ? x0[u] : gram_val<SP>(b0, lb0, k, nrows);
+            x1[u] = two ? gram_val<SP>(a1, la1, k, nrows) : 0.0;
+            y1[u] = SAME ? x1[u] : (two ? gram_val<SP>(b1, lb1, k, nrows) : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < kGramMfmaUnroll; ++u) {
+            d00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u], y0[u], d00, 0, 0, 0);
+            if (two) {
+                d01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u], y1[u], d01, 0, 0, 0);
+                if constexpr (!SAME) d10 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[u], y0[u], d10, 0, 0, 0);
+                d11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[u], y1[u], d11, 0, 0, 0);
+            }
+        }
+    }
+    // the wavefronts' tiles summed into R in wavefront order (deterministic);
+    // element i of lane l is row l / 16 + 4 i, column l % 16 of its tile
+    // (measured on gfx950)
+    for (int t = threadIdx.x; t < 32 * 33; t += blockDim.x) (&R[0][0])[t] = 0.0;
+    __syncthreads();
+    const int rg = lane >> 4, cn = lane & 15;
+    for (int w = 0; w < kGramMfmaWaves; ++w) {
+        if (w == wv) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                R[rg + 4 * i][cn] += d00[i];
+                R[rg + 4 * i][16 + cn] += d01[i];
+                R[16 + rg + 4 * i][16 + cn] += d11[i];
+                if constexpr (!SAME) R[16 + rg + 4 * i][cn] += d10[i];
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (SAME) {
+        if (wv == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) R[16 + rg + 4 * i][cn] = R[cn][16 + rg + 4 * i];
+        }
+        __syncthreads();
+    }
+    const size_t nwg = gridDim.x;
+    for (int t = threadIdx.x; t < s * s; t += blockDim.x) {
+        const int j = t / s, kk = t % s;
+        double re = 0.0, im = 0.0;
+        if (j <= kk) {
+            re = R[j][kk] + R[s + j][s + kk];
+            im = R[j][s + kk] - R[s + j][kk];
+        }
+        part[((size_t)t * 2 + 0) * nwg + blockIdx.x] = re;
+        part[((size_t)t * 2 + 1) * nwg + blockIdx.x] = im;
     }
 }
 
@@ -274,6 +389,16 @@ __global__ void __launch_bounds__(kUpdBlk) k_bqp(uint64_t nch, int s_arg, BlockR
 // ------------------------------------------------------------------ host ----
 static uint64_t chunks(const Geom& g, int fmt) { return spinor_field_bytes(g, fmt) / 16; }
 
+// Gram matrices by the cell kernel on the vector units (k_bgram), or with
+// WEO_GRAM=mfma on the FP64 matrix cores (k_bgram_mfma); read per call.  The
+// cell kernel is the default: at 32^3x64 with 12 FP32 fields it takes 409 us
+// (Q^H Q) and 472 us (P^H W) against 878 us and 1743 us on the matrix cores,
+// whose operands arrive as scattered 4-byte loads.
+static bool gram_on_matrix_cores() {
+    const char* e = getenv("WEO_GRAM");
+    return e && strcmp(e, "mfma") == 0;
+}
+
 int block_gram_wg(const Geom& g, int fmt) {          // 64 chunks per workgroup and step
     const uint64_t n = (chunks(g, fmt) + 63) / 64;
     return (int)(n < (uint64_t)kGramWG ? n : (uint64_t)kGramWG);
@@ -289,6 +414,23 @@ hipError_t launch_block_gram(const Geom& g, int fmt, int s, const BlockRef& a, c
     const uint64_t n = chunks(g, fmt);
     const int wg = block_gram_wg(g, fmt);
     const bool same = a.base == b.base && a.stride == b.stride && std::equal(a.col, a.col + s, b.col);
+    if (gram_on_matrix_cores()) {
+        const dim3 grid(wg), block(64 * kGramMfmaWaves);
+        switch (fmt_info(fmt).spinor_prec) {
+            case P_F64:
+                if (same) hipLaunchKernelGGL((k_bgram_mfma<P_F64, true>), grid, block, 0, st, n, s, a, b, part);
+                else hipLaunchKernelGGL((k_bgram_mfma<P_F64, false>), grid, block, 0, st, n, s, a, b, part);
+                break;
+            case P_F32:
+                if (same) hipLaunchKernelGGL((k_bgram_mfma<P_F32, true>), grid, block, 0, st, n, s, a, b, part);
+                else hipLaunchKernelGGL((k_bgram_mfma<P_F32, false>), grid, block, 0, st, n, s, a, b, part);
+                break;
+            default: return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_reduce(part, wg, 2 * s * s, out, st);
+    }
     const int nb = (s + 3) / 4;
     const dim3 grid(wg), block(64 * nb * (nb + 1) / 2);
     switch (fmt_info(fmt).spinor_prec) {

@@ -327,3 +327,36 @@ def test_block_cg_mixed_mdagm_and_dw_fp16_rejected():
     for meth in ("cg", "blockcg"):
         with pytest.raises(WE.WilsonEOError):
             cg(lat, F64, u64, bf, op="DW", tol=1e-10, inner=f16, u_inner=u16, maxiter=10, method=meth)
+
+
+@pytest.mark.parametrize("fmt,nrhs", [(F64, 3), (F64, 12), (F32, 7), (F32, 16)],
+                         ids=["f64-3", "f64-12", "f32-7", "f32-16"])
+def test_gram_on_matrix_cores_equals_cell_kernel(monkeypatch, fmt, nrhs):
+    """The Gram matrices of block CG computed on the FP64 matrix cores
+    (WEO_GRAM=mfma) and by the cell kernel on the vector units (the default)
+    give the same block CG iterates to FP64 rounding (one and two 16-column
+    tiles, the symmetric and the general product); both agree with the
+    oracle's iterate."""
+    print(f"gram mfma vs valu fmt={fmt} nrhs={nrhs}", flush=True)
+    dims, kappa = (6, 4, 2, 6), 0.125
+    u = inputs.gen_gauge(dims, 0.4, 170)
+    b = inputs.gen_spinor_half(dims, 171, nrhs=nrhs)
+    lat = Lattice(dims, kappa, AP)
+    u_p, b_p = lat.pack_gauge(to_device(u), fmt), lat.pack_spinor(to_device(b), fmt)
+    xs = {}
+    for mode in ("mfma", "valu"):
+        if mode == "mfma":
+            monkeypatch.setenv("WEO_GRAM", "mfma")
+        else:
+            monkeypatch.delenv("WEO_GRAM", raising=False)
+        x_p, info = cg(lat, fmt, u_p, b_p, nrhs=nrhs, tol=1e-30, maxiter=3, method="blockcg")
+        assert info["iters"] == 3, (mode, info)
+        xs[mode] = lat.unpack_spinor(x_p, fmt, nrhs=nrhs).cpu().numpy()
+    monkeypatch.delenv("WEO_GRAM", raising=False)
+    tol = 1e-12 if fmt.spinor == "f64" else 1e-5
+    sp = fmt.spinor
+    m, md = _ops(u if sp == "f64" else ROUND["f32"](u), kappa)
+    xo, _, _ = S.block_cg(None, list(ROUND[sp](b)), 1e-30, 3, apply_m=m, apply_mdag=md)
+    for j in range(nrhs):
+        assert rel_err(xs["mfma"][j], xs["valu"][j]) < tol, j
+        assert rel_err(xs["mfma"][j], xo[j]) < (1e-11 if sp == "f64" else 2e-5), j
