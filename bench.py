@@ -63,9 +63,11 @@ REAL = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
 # Launch shapes of --profile-shapes (weo_set_mrhs_shape arguments): the packed
-# FP16 link-resident kernel in several workgroup sizes and schedules, the
-# LDS-staged kernel, and one lane per (site, rhs).
-PROFILE_SHAPES = [(-4, 256, 0, 8, 0), (-4, 256, 0, 0, 0), (-4, 64, 0, 8, 0), (-4, 64, 1, 8, 0), (-4, 256, 1, 2, 0),
+# FP16 link-resident kernel in several workgroup sizes and schedules (z strips
+# of 2, 4, 8 planes, half-plane columns of 4, 8, 16), the LDS-staged kernel,
+# and one lane per (site, rhs).
+PROFILE_SHAPES = [(-4, 256, 0, 8, 0), (-4, 256, 0, 4, 0), (-4, 256, 0, 0, 0), (-4, 64, 0, 8, 0), (-4, 64, 1, 8, 0),
+                  (-4, 256, 1, 2, 0), (-4, 256, 0, -4, 0), (-4, 256, 0, -8, 0), (-4, 256, 0, -16, 0),
                   (-2, 256, 0, 8, 0), (-5, 2, 0, 4, 0), (-5, 8, 0, 4, 0), (1, 0, 0, 0, 0)]
 
 

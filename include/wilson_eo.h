@@ -121,9 +121,11 @@ int weo_format_supported(const weo_format* fmt);
  * clamped to 4 for FP64 and 8 for FP16/BF16 spinors), each walking every
  * sites-th right-hand side (all formats); here split = 0 sweeps the lattice
  * once for all right-hand sides, split = f in 1..16 once per f of them
- * (the links staged again per sweep).  persist in {0, 1}, bz in 0..64 and
+ * (the links staged again per sweep).  persist in {0, 1}, bz in -64..64 and
  * split in {0, 1} (for nr > 1) complete the shape.  bz > 0 visits the lattice in strips of bz z-planes, all t per
- * strip (ignored where the lattice or workgroup size does not allow it);
+ * strip; bz < 0 the same in columns of half an (x, y) plane (y below
+ * ly / 2, then the rest) times -bz z-planes (both ignored where the lattice
+ * or workgroup size does not allow them);
  * split = 1 gives each group of nr rhs its own workgroups and sweep of the
  * lattice.  Returns WEO_ERR_ARG for other values.  The setting is
  * process-wide. */

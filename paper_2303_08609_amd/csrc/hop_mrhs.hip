@@ -40,6 +40,16 @@ namespace weo {
 // The LDS-staged form (k_hop_lw) in MrhsCfg::nr (MrhsCfg::s then holds the
 // wavefronts per workgroup).
 constexpr int kNrLw = -5;
+// Output records of the multi-RHS kernels are written with streaming stores
+// in every precision: with many fields per site the output lines would
+// otherwise take L2 from the input records that the +-z and +-t neighbours
+// read again (FP32/18 and FP16/12 at 12 rhs: 4 % faster).  -D
+// WEO_MRHS_NT_STORE=0 restores regular stores for comparison.
+#ifdef WEO_MRHS_NT_STORE
+template <int SP> constexpr bool mrhs_nt_store() { return WEO_MRHS_NT_STORE != 0; }
+#else
+template <int SP> constexpr bool mrhs_nt_store() { return true; }
+#endif
 #ifndef LW_CROSS
 #define LW_CROSS (SP != P_F64)
 #endif
@@ -173,7 +183,7 @@ __global__ void __launch_bounds__(256) k_hop_mrhs(const MrhsParams M) {
                 if (r < M.nrhs) {
                     if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc[q]);
                     uint8_t* out = P.out + (size_t)r * P.spinor_bytes;
-                    store_rec<SP, 12, C, hop_nt_store<SP>()>(out, P.g.vh, ih, acc[q]);
+                    store_rec<SP, 12, C, mrhs_nt_store<SP>()>(out, P.g.vh, ih, acc[q]);
                     if (P.partial) hop_reduce<SP>(P, (size_t)r, ih, acc[q], nrm[q], dre[q], dim[q]);
                 }
             }
@@ -293,7 +303,7 @@ __global__ void __launch_bounds__(256) k_hop_lr(const MrhsParams M) {
                 for (int k = 0; k < 12; ++k) acc[k] = czero<C>();
                 lr_step<SP, LP, L12, DAG, CPH, D, 0>(P, in, in_next, nb, lk, ring, acc);
                 if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc);
-                store_rec<SP, 12>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
+                store_rec<SP, 12, C, mrhs_nt_store<SP>()>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
                 if (P.partial) hop_reduce<SP>(P, (size_t)r, ih, acc, nrm, dre, dim);
             }
             if (P.partial)
@@ -450,7 +460,7 @@ __global__ void __launch_bounds__(64 * lw_maxw<SP>()) k_hop_lw(const MrhsParams 
                 for (int k = 0; k < 12; ++k) acc[k] = czero<C>();
                 lw_step<SP, LP, L12, DAG, CPH, D, 0>(P, lds, lo, in, in_next, nb, ring, acc);
                 if (P.y) hop_addends<SP>(P, (size_t)r, ih, acc);
-                store_rec<SP, 12, C, hop_nt_store<SP>()>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
+                store_rec<SP, 12, C, mrhs_nt_store<SP>()>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
                 if (P.partial) hop_reduce<SP, DOT>(P, (size_t)r, ih, acc, nrm, dre, dim);
             }
             if (P.partial) hop_partials_out<DOT>(P, (size_t)r, base >> 6, nchunk, lane == 0, nrm, dre, dim);
@@ -668,7 +678,7 @@ __global__ void __launch_bounds__(256) k_hop_lr16(const MrhsParams M) {
                 for (int k = 0; k < 12; ++k) acc[k] = make_float2(0.f, 0.f);
                 h16_step<DAG, D, 0>(P, in, in_next, nb, lk, ring, acc);
                 if (P.y) hop_addends<P_F16>(P, (size_t)r, ih, acc);
-                store_rec<P_F16, 12>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
+                store_rec<P_F16, 12, float2, mrhs_nt_store<P_F16>()>(P.out + (size_t)r * P.spinor_bytes, n, ih, acc);
                 if (P.partial) hop_reduce<P_F16>(P, (size_t)r, ih, acc, nrm, dre, dim);
             }
             if (P.partial)
@@ -908,6 +918,9 @@ struct TuneEntry {
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneEntry> g_tune;
 
+// The half-plane column walks (bz < 0) are not candidates: at 32^3x64 with
+// 12 rhs they were never faster than the z strips (FP16/12 406 us against
+// 399 us, FP32/12 728 against 725 us); weo_set_mrhs_shape still selects them.
 std::vector<MrhsCfg> candidates(const HopLaunch& h) {
     std::vector<MrhsCfg> v;
     v.push_back({1, 0, 0, 0, 0});
@@ -971,7 +984,7 @@ bool tuning_verbose() {
 // An entry is used only if its shape is among the current candidates for
 // that key (so a stale or edited file can pick a slower shape, never an
 // invalid launch).  New results are appended, one line per write.
-constexpr int kTuneCacheVersion = 3;
+constexpr int kTuneCacheVersion = 4;
 
 const char* tune_cache_path() {
     const char* p = getenv("WILSON_EO_TUNE_CACHE");
@@ -1108,7 +1121,7 @@ int set_mrhs_shape(int nr, int sites, int persist, int bz, int split) {
         return 0;
     }
     if (nr == kNrLw) {
-        if (!lw_waves_ok(sites) || (persist != 0 && persist != 1) || bz < 0 || bz > 64 || split < 0 ||
+        if (!lw_waves_ok(sites) || (persist != 0 && persist != 1) || bz < -64 || bz > 64 || split < 0 ||
             split > 16)       // 16: the most right-hand sides of a launch
             return -1;
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1120,7 +1133,7 @@ int set_mrhs_shape(int nr, int sites, int persist, int bz, int split) {
     if (nr < 0) {
         if (sites != 64 && sites != 128 && sites != 256) return -1;
         if (persist != 0 && persist != 1) return -1;
-        if (bz < 0 || bz > 64) return -1;
+        if (bz < -64 || bz > 64) return -1;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_forced = {nr, sites, persist, bz, 0};
         return 0;
@@ -1128,7 +1141,7 @@ int set_mrhs_shape(int nr, int sites, int persist, int bz, int split) {
     if (nr != 2 && nr != 3 && nr != 4 && nr != 6) return -1;
     if (sites != 64 && sites != 128 && sites != 256) return -1;
     if (persist != 0 && persist != 1) return -1;
-    if (bz < 0 || bz > 64) return -1;
+    if (bz < -64 || bz > 64) return -1;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_forced = {nr, sites, persist, bz, split};
     return 0;

@@ -69,7 +69,7 @@ static int check_remap() {
 static int check_sched(const int dims[4]) {
     const Geom g = make_geom(dims);
     for (uint32_t S : {64u, 128u, 256u}) {
-        for (int bz : {0, 2, 4, 8}) {
+        for (int bz : {0, 2, 4, 8, -1, -2, -4, -8, -16}) {
             const Sched sc = make_sched(g, bz, S);
             if (bz && sc.bz == 0) continue;
             const uint32_t nblk = (g.vh + S - 1) / S;

@@ -350,11 +350,27 @@ __host__ __device__ __forceinline__ Nbr neighbours(const Geom& g, const Site& s)
 // touched again within a window of about bz planes instead of a whole
 // t-slice (this matters when many right-hand sides multiply the working set).
 // Needs plane % S == 0 (S = sites per workgroup) and lz % bz == 0.
+// bz < 0: the same with each (x, y) plane cut into two halves along y, all
+// strips of the first half before the second: a column of half planes
+// times |bz| z values walks t, which halves the window between +-t reuses
+// for one more halo along y.  Needs plane % (2 S) == 0 and lz % |bz| == 0.
 using Sched = SchedHost;    // built on the host by make_sched (weo_geom.h)
 
 __host__ __device__ __forceinline__ uint32_t block_first_site(const Sched& s, const Geom& g, uint32_t blk,
                                                               uint32_t S) {
     if (s.bz == 0) return blk * S;
+    if (s.bz < 0) {
+        const uint32_t q = fdiv(blk, s.d_bpp);
+        const uint32_t c = blk - q * s.d_bpp.d;        // block within the half plane
+        const uint32_t q2 = fdiv(q, s.d_bz);
+        const uint32_t zi = q - q2 * s.d_bz.d;
+        const uint32_t q3 = fdiv(q2, s.d_lt);
+        const uint32_t t = q2 - q3 * s.d_lt.d;
+        const uint32_t half = fdiv(q3, s.d_nzb);
+        const uint32_t zb = q3 - half * s.d_nzb.d;
+        const uint32_t z = zb * s.d_bz.d + zi;
+        return (half * s.d_bpp.d + c) * S + s.plane * (z + (uint32_t)g.lz * t);
+    }
     const uint32_t q = fdiv(blk, s.d_bpp);
     const uint32_t c = blk - q * s.d_bpp.d;
     const uint32_t q2 = fdiv(q, s.d_bz);

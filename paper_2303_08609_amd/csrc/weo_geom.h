@@ -54,19 +54,27 @@ inline Geom make_geom(const int dims[4]) {
 // Schedule descriptor for block_first_site (weo_device.h); bz = 0 when the
 // requested strip height does not fit the lattice or the workgroup size.
 struct SchedHost {
-    int bz;
+    int bz;             // 0: lexicographic; > 0: z strips; < 0: half-plane columns
     uint32_t plane;
-    FastDiv d_bpp, d_bz, d_lt;
+    FastDiv d_bpp;      // blocks per plane (strips) or per half plane (columns)
+    FastDiv d_bz, d_lt;
+    FastDiv d_nzb;      // strips of |bz| planes along z (columns)
 };
 
+// bz > 0 needs plane % S == 0, bz < 0 plane % (2 S) == 0; both need
+// lz % |bz| == 0.  Otherwise the schedule is lexicographic (bz = 0).
 inline SchedHost make_sched(const Geom& g, int bz, uint32_t sites_per_block) {
     SchedHost s;
     s.plane = (uint32_t)g.lxh * (uint32_t)g.ly;
     s.bz = 0;
-    if (bz > 0 && sites_per_block > 0 && s.plane % sites_per_block == 0 && g.lz % bz == 0) s.bz = bz;
-    s.d_bpp = make_fastdiv(s.bz ? s.plane / sites_per_block : 1);
-    s.d_bz = make_fastdiv(s.bz ? (uint32_t)s.bz : 1);
+    const uint32_t S = sites_per_block;
+    const int az = bz < 0 ? -bz : bz;
+    const uint32_t parts = bz < 0 ? 2u : 1u;
+    if (bz != 0 && S > 0 && s.plane % (parts * S) == 0 && g.lz % az == 0) s.bz = bz;
+    s.d_bpp = make_fastdiv(s.bz ? s.plane / (parts * S) : 1);
+    s.d_bz = make_fastdiv(s.bz ? (uint32_t)az : 1);
     s.d_lt = make_fastdiv((uint32_t)g.lt);
+    s.d_nzb = make_fastdiv(s.bz ? (uint32_t)(g.lz / az) : 1);
     return s;
 }
 

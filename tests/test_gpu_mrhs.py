@@ -55,6 +55,36 @@ def test_every_shape_matches_oracle(fmt_t, dims):
                 assert rel_err(got[r], ref[r]) <= TOL[fmt_t[0]], (shape, dag, r)
 
 
+COLUMN_SHAPES = [(d, s, p, bz, 0) for d in (-1, -2, -3, -4) for s in (64, 256) for p in (0, 1) for bz in (-1, -2, -4)] + \
+    [(-5, w, p, bz, f) for w in (2, 4) for p in (0, 1) for bz in (-2, -4) for f in (0, 3)] + \
+    [(nr, 64, 0, -2, sp) for nr in (2, 3) for sp in (0, 1)]
+
+
+@pytest.mark.parametrize("fmt_t", [("f32", "f32", 18), ("f16", "f16", 12), ("f64", "f64", 12), ("bf16", "f16", 12)],
+                         ids=["f32-18", "f16-12", "f64-12", "bf16-12"])
+@pytest.mark.parametrize("dims", [(32, 32, 4, 4), (16, 16, 4, 6)], ids=["plane512", "plane128"])
+def test_column_schedules_match_oracle(fmt_t, dims):
+    """Workgroups that walk columns of half (x, y) planes times 1, 2 or 4
+    z-planes along t (negative bz) produce every output site once and
+    correctly: 32x32 planes (512 half sites: 256-site workgroups take the
+    columns too) and 16x16 planes (128 half sites: only 64-site workgroups
+    do, the rest fall back to the lexicographic walk), both parities and
+    dagger, 12 sources."""
+    nrhs = 12
+    print(f"column shapes fmt={fmt_t} dims={dims}", flush=True)
+    lat, fmt, u_d, x_d, u_o, psi_o = _setup(dims, fmt_t, nrhs, seed=760)
+    ph = np.array(AP, dtype=np.complex128)
+    want = {(par, dag): [W.hop_eo(u_o, psi_o[r], 1 - par, ph, dagger=dag) for r in range(nrhs)]
+            for par in (0, 1) for dag in (False, True)}
+    for shape in COLUMN_SHAPES:
+        assert WE.weo_set_mrhs_shape(*shape) == WE.WEO_OK
+        for (par, dag), ref in want.items():
+            out = lat.hop(u_d, x_d, fmt, out_parity=par, dagger=dag, nrhs=nrhs)
+            got = lat.unpack_spinor(out, fmt, nrhs=nrhs).cpu().numpy()
+            for r in range(nrhs):
+                assert rel_err(got[r], ref[r]) <= TOL[fmt_t[0]], (shape, par, dag, r)
+
+
 PAIR_SHAPES = [(d, s, p, bz, 0) for d in (-2, -4) for s in (64, 128, 256) for p in (0, 1) for bz in (0, 2)]
 
 
@@ -181,7 +211,9 @@ def test_bad_shape_rejected():
     assert WE.weo_set_mrhs_shape(5, 64, 0, 0, 0) == WE.WEO_ERR_ARG
     assert WE.weo_set_mrhs_shape(2, 96, 0, 0, 0) == WE.WEO_ERR_ARG
     assert WE.weo_set_mrhs_shape(2, 64, 2, 0, 0) == WE.WEO_ERR_ARG
-    assert WE.weo_set_mrhs_shape(2, 64, 0, -1, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(2, 64, 0, -65, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(-3, 64, 0, 65, 0) == WE.WEO_ERR_ARG
+    assert WE.weo_set_mrhs_shape(-5, 4, 0, -65, 0) == WE.WEO_ERR_ARG
     assert WE.weo_set_mrhs_shape(2, 64, 0, 0, 2) == WE.WEO_ERR_ARG
     assert WE.weo_set_mrhs_shape(-5, 5, 0, 0, 0) == WE.WEO_ERR_ARG
     assert WE.weo_set_mrhs_shape(-5, 64, 0, 0, 0) == WE.WEO_ERR_ARG
